@@ -1,0 +1,37 @@
+"""CPU oracle for the CWENO reconstruction of Sec. 2.1 -- TEST INFRASTRUCTURE.
+
+A plain, slow, FP64 implementation of what the library computes, written
+from the paper and sharing no code with the library (no kernels, headers,
+helpers, tables or generators).  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import it; the library never does, and the
+library never falls back to it.
+
+Parity status of each part (what pins it, from outside the oracle itself):
+
+* basis        -- exact rational orthogonality, closed-form linear functions,
+                  known Gram diagonals, degree count against the paper's DOF
+                  totals (eq. cwenoM).
+* Sigma        -- quadratic form equals sum_alpha int (d^alpha P)^2 from an
+                  independent symbolic differentiation; closed form for
+                  linear polynomials.
+* quadrature   -- exact on monomials up to its degree.
+* stencils     -- stencil sizes printed in the paper's stencil figures
+                  (n_e = 12 in 2-D, 30 in 3-D at M = 2); brute-force
+                  re-derivation of the ring rule; cone membership on hand-built
+                  triangles.
+* P_opt        -- polynomial reproduction on arbitrary meshes; brute-force
+                  exact-rational KKT solve on tiny meshes.
+* P_s, P0, w   -- linear data reproduced with omega = lambda; constant data
+                  gives sigma = 0; exact-rational pipeline on tiny meshes;
+                  conservation; convergence on smooth data; no overshoot at
+                  jumps.
+* dropped-sector rule -- parity unpinned (the paper assumes non-degenerate
+                  stencils and gives no rule).
+"""
+from .basis import n_basis, sigma_matrix, evaluate as evaluate_basis, index_list
+from .cweno import CwenoOracle, Options, linear_weights, stencil_size, evaluate_polynomial
+from .stencils import StencilError, face_neighbours
+
+__all__ = ["n_basis", "sigma_matrix", "evaluate_basis", "index_list", "CwenoOracle",
+           "Options", "linear_weights", "stencil_size", "evaluate_polynomial",
+           "StencilError", "face_neighbours"]
