@@ -30,7 +30,7 @@ import numpy as np
 from .geometry import Geometry, barycentric
 
 CONE_TOL = 1e-12
-MAX_RINGS = 8
+MAX_RINGS = 16
 # A stencil cell farther than this fraction of the period from cell i (along
 # a periodic axis) makes the minimum-image reading unsafe: the mesh is too
 # coarse for the stencil.

@@ -134,7 +134,7 @@ def test_periodic_meshes_fill_every_sector():
 
 
 def test_coarse_periodic_mesh_rejected():
-    m = tri_mesh(3, 0.15, 1)
+    m = tri_mesh(4, 0.15, 14)
     o = CwenoOracle(m.vertices, m.cells, m.box, Options(degree=3))
     with pytest.raises(StencilError):
         o.stencils(0)
