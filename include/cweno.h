@@ -1,0 +1,207 @@
+/*
+ * cweno.h -- C ABI of the MI355X CWENO reconstruction library.
+ *
+ * The library implements the central WENO reconstruction of Dumbser,
+ * Boscheri, Semplice and Russo, "Central WENO schemes for hyperbolic
+ * conservation laws on fixed and moving unstructured meshes" (arXiv
+ * 1612.09335), Sec. 2.1, on conforming triangle (d = 2) and tetrahedron
+ * (d = 3) meshes with fixed (Eulerian) geometry: from the cell averages of
+ * every variable it returns, per cell, the coefficients of one polynomial of
+ * degree M that is defined everywhere in the cell (abstract; Sec. 2.1).
+ *
+ * Conventions
+ *  - Every function returns a cweno_status: 0 on success, a negative code on
+ *    failure.  Nothing throws across the ABI.  cweno_last_error() returns a
+ *    human-readable detail of the calling thread's last failure.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *    device memory on the current device.  Streams are hipStream_t passed as
+ *    void* (NULL = the default stream).
+ *  - Cell c's reference frame is fixed by its vertex order: vertex 0 maps to
+ *    the origin of the unit simplex and vertex k to the k-th unit vector
+ *    (Sec. 2, eq. xietaTransf).  All output coefficients are in the
+ *    orthonormal Dubiner basis of that frame: basis function 0 is the
+ *    constant 1, functions 1..d are linear, ordered by total degree, then by
+ *    the collapsed-coordinate indices p descending and q descending; they are
+ *    orthonormal w.r.t. (1/|T_E|) times the integral over the unit simplex.
+ *  - Periodic boxes use the minimum-image convention per periodic axis.
+ *  - Device arrays are structure-of-arrays with the cell index fastest:
+ *    q[v][i] (n_vars x n_cells) and coeffs[v][l][i] (n_vars x n_basis x n_cells).
+ */
+#ifndef CWENO_H
+#define CWENO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CWENO_ABI_VERSION 1
+
+typedef enum {
+  CWENO_OK = 0,
+  CWENO_E_ARG = -1,       /* invalid argument (NULL pointer, bad size, unsupported combination) */
+  CWENO_E_MESH = -2,      /* degenerate cell, face shared by > 2 cells, vertex id out of range   */
+  CWENO_E_STENCIL = -3,   /* a central stencil cannot be filled                                   */
+  CWENO_E_RANK = -4,      /* rank-deficient least-squares system                                  */
+  CWENO_E_PERIODIC = -5,  /* a stencil reaches too far across a periodic box (mesh too coarse)    */
+  CWENO_E_NOMEM = -6,     /* host or device allocation failed                                     */
+  CWENO_E_BUDGET = -7,    /* request exceeds a memory budget                                      */
+  CWENO_E_HIP = -8,       /* a HIP runtime call failed                                            */
+  CWENO_E_BUSY = -9,      /* resource in use                                                      */
+  CWENO_E_CANCELLED = -10 /* request cancelled                                                    */
+} cweno_status;
+
+typedef enum {
+  CWENO_F64 = 0,  /* double precision */
+  CWENO_F32 = 1   /* single precision */
+} cweno_dtype;
+
+/* Which precisions of the per-cell operators a mesh keeps resident. */
+typedef enum {
+  CWENO_OPS_F64 = 0,
+  CWENO_OPS_F32 = 1,
+  CWENO_OPS_BOTH = 2
+} cweno_ops;
+
+typedef enum {
+  /* Sec. 2.1: sector s holds the cell and the nearest cells whose barycentre
+   * lies in the open cone with apex at vertex s spanned by the edges towards
+   * the other vertices (the cone through the face opposite vertex s). */
+  CWENO_SECTOR_CONE = 0,
+  /* Sector s = the cell and its face neighbours except the one across the
+   * face opposite vertex s (exactly d+1 cells). */
+  CWENO_SECTOR_FACE = 1
+} cweno_sector_rule;
+
+/* Option flags. */
+#define CWENO_FLAG_HOST_ONLY 1u       /* build tables/operators on the host only; no device upload */
+#define CWENO_FLAG_SIGMA0_POPT 2u     /* indicator of the central polynomial from P_opt, not P_0   */
+#define CWENO_FLAG_LINEAR_WEIGHTS 4u  /* diagnostic: omega := lambda (w = P_opt)                   */
+
+/* Reconstruction options.  A zero-initialised struct gives the defaults. */
+typedef struct {
+  double periodic[3];      /* period per axis; 0 = not periodic                                  */
+  double stencil_factor;   /* central stencil n_e = ceil(f * n_basis); 0 -> f = d (Sec. 2.1)   */
+  double lambda0;          /* central linear weight in (0,1); 0 -> 0.95; negative -> the paper's
+                              pair (1e5 central, 1 per sector, Sec. 2.1) normalised to sum 1.
+                              Each sector gets (1 - lambda0)/(d+1).                              */
+  double eps;              /* eps of the nonlinear weights; 0 -> 1e-14 (Sec. 2.1)              */
+  int r;                   /* exponent r of the nonlinear weights; 0 -> 4 (Sec. 2.1)            */
+  int ops;                 /* cweno_ops: operator precisions kept on the device; default F64    */
+  int sector_rule;         /* cweno_sector_rule                                                  */
+  unsigned flags;          /* CWENO_FLAG_*                                                       */
+} cweno_options;
+
+typedef struct cweno_mesh cweno_mesh;
+
+/*
+ * cweno_mesh_create -- register a mesh and precompute its reconstruction
+ * operators (Sec. 2.1: stencils and inverted least-squares matrices are
+ * computed once and stored for fixed meshes).
+ *
+ *  dim          2 (triangles) or 3 (tetrahedra)
+ *  n_vertices   number of vertices (> 0)
+ *  vertices     host, [n_vertices][dim] doubles; copied
+ *  n_cells      number of cells (> 0, < 2^31)
+ *  cells        host, [n_cells][dim+1] int32 vertex ids, 0-based; copied.  The
+ *               order of each row fixes the cell's reference frame.
+ *  degree       polynomial degree M, 1..4
+ *  opt          options (NULL = defaults)
+ *  hip_stream   stream for the device upload (NULL = default); the call
+ *               synchronises it before returning
+ *  out          receives the new mesh; owned by the caller, free with
+ *               cweno_mesh_destroy
+ *
+ * Steps (host, FP64, multithreaded): minimum-image geometry, face adjacency,
+ * central and sectorial stencils (Sec. 2.1, eq. stencil; breadth-first rings
+ * of face neighbours ordered by squared barycentre distance, ties by lower
+ * index), stencil averages of the basis in each cell's reference frame
+ * (Gaussian quadrature), the least-squares pseudo-inverse for P_opt (eq.
+ * CWENO:Popt, reduced exactly to an unconstrained problem on differences
+ * because the basis has zero mean: p_0 = Q_i, p_{1..} = pinv(A') dQ), the
+ * inverses of the sectorial P1 systems (eq. CWENO:Ps), and the universal
+ * oscillation matrix Sigma.  A sector that cannot be filled or whose system
+ * has condition number above 1e10 is dropped (its linear weight becomes 0,
+ * the others are renormalised).
+ *
+ * Errors: CWENO_E_ARG, CWENO_E_MESH, CWENO_E_STENCIL, CWENO_E_RANK,
+ * CWENO_E_PERIODIC, CWENO_E_NOMEM, CWENO_E_HIP.  On error *out is NULL.
+ */
+cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertices,
+                               int64_t n_cells, const int32_t* cells, int degree,
+                               const cweno_options* opt, void* hip_stream, cweno_mesh** out);
+
+/* Release a mesh and its device memory.  NULL is accepted.  The caller must
+ * ensure no reconstruction on it is still running. */
+cweno_status cweno_mesh_destroy(cweno_mesh* mesh);
+
+/*
+ * cweno_mesh_info -- sizes of a mesh.  Any output pointer may be NULL.
+ *  n_cells       number of cells
+ *  n_basis       basis size n_basis(M, d) = (1/d!) prod_{l=1..d} (M + l) (eq. cwenoM)
+ *  n_e           central stencil size (cell included)
+ *  gather_len    per-cell gather list length: n_e - 1 plus the mesh-wide maximum
+ *                number of sector cells outside the central stencil
+ *  device_bytes  bytes of device memory held by the mesh
+ *  n_dropped     number of dropped sectors over the whole mesh
+ */
+cweno_status cweno_mesh_info(const cweno_mesh* mesh, int64_t* n_cells, int* n_basis, int* n_e,
+                             int* gather_len, int64_t* device_bytes, int64_t* n_dropped);
+
+/*
+ * cweno_mesh_tables -- host copies of the integer tables (any pointer may be NULL).
+ *  face_nbr  [n_cells][d+1]: the cell across the face opposite local vertex k, -1 = boundary
+ *  stencil   [n_cells][n_e]: central stencil, the cell itself first (Sec. 2.1, j(1) = i)
+ *  sectors   [n_cells][d+1][d+1]: sector s, the cell itself first; a dropped sector is a row of -1
+ */
+cweno_status cweno_mesh_tables(const cweno_mesh* mesh, int32_t* face_nbr, int32_t* stencil,
+                               int32_t* sectors);
+
+/*
+ * cweno_mesh_operators -- host copies of the FP64 per-cell operators for one
+ * cell (any pointer may be NULL).
+ *  pinv   [(n_basis-1)][(n_e-1)]: P_opt coefficients 1.. = pinv * (Q_stencil[1..] - Q_i)
+ *  binv   [d+1][d][d]: sector s linear coefficients 1..d = binv_s * (Q_sector[1..] - Q_i)
+ *  sigma  [(n_basis-1)][(n_basis-1)]: oscillation matrix without the constant row/column
+ */
+cweno_status cweno_mesh_operators(const cweno_mesh* mesh, int64_t cell, double* pinv, double* binv,
+                                  double* sigma);
+
+/*
+ * cweno_reconstruct -- the reconstruction of Sec. 2.1 for every cell and
+ * variable of a mesh: (a) P_opt from the stored pseudo-inverse (eq.
+ * CWENO:Popt), (b) the d+1 sectorial P1 polynomials (eq. CWENO:Ps), (c)
+ * P_0 = (P_opt - sum_s lambda_s P_s)/lambda_0 (eq. CWENO:P0), (d) the
+ * oscillation indicators sigma_s = p_s^T Sigma p_s, (e) the nonlinear weights
+ * omega_s = lambda_s/(sigma_s+eps)^r normalised (eqs. weights, weights2) and
+ * the blend w = sum_s omega_s P_s (eq. CWENO:Prec).
+ *
+ *  n_vars      number of variables (>= 1)
+ *  dtype       precision of q, coeffs, sigma, omega and of the arithmetic;
+ *              the mesh must hold operators of that precision
+ *  q           device, [n_vars][n_cells] cell averages
+ *  coeffs      device, [n_vars][n_basis][n_cells] output; coeffs[v][0][i] is a
+ *              bitwise copy of q[v][i] (conservation)
+ *  sigma       optional device output [n_vars][d+2][n_cells] (index 0 = central), or NULL
+ *  omega       optional device output [n_vars][d+2][n_cells], or NULL
+ *  hip_stream  stream to launch on (NULL = default)
+ *
+ * Asynchronous: it enqueues kernels and returns; it neither allocates nor
+ * synchronises.  Buffers are owned by the caller and must stay valid until
+ * the stream has executed the work.  Errors: CWENO_E_ARG (bad sizes, host-only
+ * mesh, missing operator precision), CWENO_E_HIP (launch failure).
+ */
+cweno_status cweno_reconstruct(const cweno_mesh* mesh, int n_vars, cweno_dtype dtype,
+                               const void* q, void* coeffs, void* sigma, void* omega,
+                               void* hip_stream);
+
+const char* cweno_status_string(cweno_status status);
+const char* cweno_last_error(void);
+int cweno_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CWENO_H */

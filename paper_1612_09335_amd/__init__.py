@@ -1,0 +1,184 @@
+"""MI355X CWENO reconstruction on unstructured simplex meshes (arXiv 1612.09335).
+
+Thin Python binding of the C ABI in ``include/cweno.h``: argument marshalling
+only.  Every step of the reconstruction runs in ``libcweno.so`` (host
+precompute in C++, reconstruction in gfx950 HIP kernels); PyTorch tensors
+provide device memory and streams.  There is no fallback: if the library is
+missing, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcweno.so")
+
+F64, F32 = 0, 1
+OPS = {"f64": 0, "f32": 1, "both": 2}
+SECTOR_RULES = {"cone": 0, "face": 1}
+FLAG_HOST_ONLY, FLAG_SIGMA0_POPT, FLAG_LINEAR_WEIGHTS = 1, 2, 4
+
+STATUS = {0: "CWENO_OK", -1: "CWENO_E_ARG", -2: "CWENO_E_MESH", -3: "CWENO_E_STENCIL",
+          -4: "CWENO_E_RANK", -5: "CWENO_E_PERIODIC", -6: "CWENO_E_NOMEM", -7: "CWENO_E_BUDGET",
+          -8: "CWENO_E_HIP", -9: "CWENO_E_BUSY", -10: "CWENO_E_CANCELLED"}
+
+SYMBOLS = ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_mesh_tables",
+           "cweno_mesh_operators", "cweno_reconstruct", "cweno_status_string", "cweno_last_error",
+           "cweno_abi_version")
+
+
+class CwenoError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{self.name}: {detail}")
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("periodic", ctypes.c_double * 3), ("stencil_factor", ctypes.c_double),
+                ("lambda0", ctypes.c_double), ("eps", ctypes.c_double), ("r", ctypes.c_int),
+                ("ops", ctypes.c_int), ("sector_rule", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1612_09335_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32p = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)
+    lib.cweno_mesh_create.argtypes = [ctypes.c_int, i64, vp, i64, vp, ctypes.c_int, ctypes.POINTER(_Options),
+                                      vp, ctypes.POINTER(vp)]
+    lib.cweno_mesh_destroy.argtypes = [vp]
+    lib.cweno_mesh_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.cweno_mesh_tables.argtypes = [vp, vp, vp, vp]
+    lib.cweno_mesh_operators.argtypes = [vp, i64, vp, vp, vp]
+    lib.cweno_reconstruct.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
+    lib.cweno_status_string.argtypes = [ctypes.c_int]
+    lib.cweno_status_string.restype = ctypes.c_char_p
+    lib.cweno_last_error.restype = ctypes.c_char_p
+    for name in ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_mesh_tables",
+                 "cweno_mesh_operators", "cweno_reconstruct"):
+        getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+
+def _check(st: int):
+    if st != 0:
+        raise CwenoError(st, lib.cweno_last_error().decode())
+
+
+def n_basis(M: int, d: int) -> int:
+    """eq. cwenoM: (1/d!) prod_{l=1..d} (M + l)."""
+    return (M + 1) * (M + 2) // 2 if d == 2 else (M + 1) * (M + 2) * (M + 3) // 6
+
+
+class Mesh:
+    """A registered mesh with its reconstruction operators (cweno_mesh_create)."""
+
+    def __init__(self, vertices, cells, degree: int, periodic=(0.0, 0.0, 0.0), stencil_factor: float = 0.0,
+                 lambda0: float = 0.0, eps: float = 0.0, r: int = 0, ops: str = "f64",
+                 sector_rule: str = "cone", sigma0_popt: bool = False, linear_weights: bool = False,
+                 host_only: bool = False, stream=None):
+        V = np.ascontiguousarray(vertices, dtype=np.float64)
+        C = np.ascontiguousarray(cells, dtype=np.int32)
+        self.dim = int(V.shape[1])
+        self.degree = int(degree)
+        o = _Options()
+        for a, L in enumerate(tuple(periodic)[:3]):
+            o.periodic[a] = float(L)
+        o.stencil_factor = float(stencil_factor)
+        o.lambda0 = float(lambda0)
+        o.eps = float(eps)
+        o.r = int(r)
+        o.ops = OPS[ops]
+        o.sector_rule = SECTOR_RULES[sector_rule]
+        o.flags = ((FLAG_HOST_ONLY if host_only else 0) | (FLAG_SIGMA0_POPT if sigma0_popt else 0)
+                   | (FLAG_LINEAR_WEIGHTS if linear_weights else 0))
+        self.ops = ops
+        self.host_only = host_only
+        h = ctypes.c_void_p()
+        st = lib.cweno_mesh_create(self.dim, V.shape[0], V.ctypes.data, C.shape[0], C.ctypes.data,
+                                   self.degree, ctypes.byref(o), _stream_ptr(stream), ctypes.byref(h))
+        _check(st)
+        self._h = h
+        n, nb, ne, g, db, nd = (ctypes.c_int64(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(),
+                                ctypes.c_int64(), ctypes.c_int64())
+        _check(lib.cweno_mesh_info(h, ctypes.byref(n), ctypes.byref(nb), ctypes.byref(ne), ctypes.byref(g),
+                                   ctypes.byref(db), ctypes.byref(nd)))
+        self.n_cells, self.n_basis, self.n_e = n.value, nb.value, ne.value
+        self.gather_len, self.device_bytes, self.n_dropped = g.value, db.value, nd.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.cweno_mesh_destroy(h)
+            self._h = None
+
+    def tables(self):
+        """Host copies: face_nbr [n, d+1], stencil [n, n_e], sectors [n, d+1, d+1]."""
+        d = self.dim
+        fn = np.empty((self.n_cells, d + 1), dtype=np.int32)
+        st = np.empty((self.n_cells, self.n_e), dtype=np.int32)
+        se = np.empty((self.n_cells, d + 1, d + 1), dtype=np.int32)
+        _check(lib.cweno_mesh_tables(self._h, fn.ctypes.data, st.ctypes.data, se.ctypes.data))
+        return dict(face_nbr=fn, stencil=st, sectors=se)
+
+    def operators(self, cell: int):
+        """FP64 operators of one cell: pinv [nb-1, n_e-1], binv [d+1, d, d], sigma [nb-1, nb-1]."""
+        d, nb, ne = self.dim, self.n_basis, self.n_e
+        P = np.empty((nb - 1, ne - 1))
+        B = np.empty((d + 1, d, d))
+        S = np.empty((nb - 1, nb - 1))
+        _check(lib.cweno_mesh_operators(self._h, int(cell), P.ctypes.data, B.ctypes.data, S.ctypes.data))
+        return P, B, S
+
+    def sigma_matrix(self):
+        nb = self.n_basis
+        S = np.empty((nb - 1, nb - 1))
+        _check(lib.cweno_mesh_operators(self._h, 0, None, None, S.ctypes.data))
+        return S
+
+    def reconstruct(self, q, out=None, sigma=None, omega=None, stream=None):
+        """cweno_reconstruct on torch CUDA tensors: q [n_vars, n_cells] -> coeffs [n_vars, n_basis, n_cells].
+
+        ``sigma`` / ``omega`` may be preallocated [n_vars, d+2, n_cells] tensors (or None).
+        Asynchronous on ``stream`` (a torch stream; None = torch's current stream).
+        """
+        import torch
+        if not q.is_cuda or q.dim() != 2 or q.shape[1] != self.n_cells or not q.is_contiguous():
+            raise ValueError("q must be a contiguous CUDA tensor [n_vars, n_cells]")
+        dt = {torch.float64: F64, torch.float32: F32}.get(q.dtype)
+        if dt is None:
+            raise ValueError("q must be float64 or float32")
+        nv = q.shape[0]
+        if out is None:
+            out = torch.empty((nv, self.n_basis, self.n_cells), dtype=q.dtype, device=q.device)
+        for t, shape in ((out, (nv, self.n_basis, self.n_cells)), (sigma, (nv, self.dim + 2, self.n_cells)),
+                         (omega, (nv, self.dim + 2, self.n_cells))):
+            if t is not None and (tuple(t.shape) != shape or t.dtype != q.dtype or not t.is_contiguous()
+                                  or t.device != q.device):
+                raise ValueError(f"output tensor must be contiguous {q.dtype} {shape} on {q.device}")
+        if stream is None:
+            stream = torch.cuda.current_stream(q.device)
+        _check(lib.cweno_reconstruct(self._h, nv, dt, q.data_ptr(), out.data_ptr(),
+                                     None if sigma is None else sigma.data_ptr(),
+                                     None if omega is None else omega.data_ptr(), _stream_ptr(stream)))
+        return out
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return getattr(stream, "cuda_stream", None)
+
+
+__all__ = ["Mesh", "CwenoError", "n_basis", "lib", "LIB_PATH", "SYMBOLS"]

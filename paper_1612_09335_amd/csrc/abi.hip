@@ -1,0 +1,314 @@
+// C ABI of the CWENO reconstruction library: mesh registration (host
+// precompute + device residency) and the reconstruction launch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cweno.h"
+#include "dispatch.hpp"
+#include "host.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+cweno_status fail(cweno_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct cweno_mesh {
+  int d = 2, M = 1, nb = 0, n_e = 0, G = 0;
+  int64_t nc = 0, Np = 0;
+  double lam[5] = {0, 0, 0, 0, 0};
+  double eps = 1e-14;
+  int r = 4;
+  unsigned flags = 0;
+  int ops = CWENO_OPS_F64;
+  int64_t n_dropped = 0;
+  // host copies
+  std::vector<int32_t> nbr, central, sectors;
+  cweno::Operators op;  // FP64 operators (host copy kept only for host-only meshes)
+  // device residency
+  int device = -1;
+  DevBuf pinv64, binv64, sigma64, pinv32, binv32, sigma32, gidx, secpos, mask;
+  int64_t device_bytes = 0;
+
+  ~cweno_mesh() {
+    for (DevBuf* b : {&pinv64, &binv64, &sigma64, &pinv32, &binv32, &sigma32, &gidx, &secpos, &mask})
+      if (b->p) (void)hipFree(b->p);
+  }
+};
+
+namespace {
+
+cweno_status upload(DevBuf& b, const void* src, size_t bytes, hipStream_t s, int64_t& total) {
+  if (bytes == 0) return CWENO_OK;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return fail(CWENO_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  total += (int64_t)bytes;
+  e = hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("hipMemcpyAsync failed: ") + hipGetErrorString(e));
+  // pageable source: wait before the host buffer may be released
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("hipStreamSynchronize failed: ") + hipGetErrorString(e));
+  return CWENO_OK;
+}
+
+cweno_status upload_f32(DevBuf& b, const std::vector<double>& src, hipStream_t s, int64_t& total) {
+  std::vector<float> tmp(src.size());
+  for (size_t t = 0; t < src.size(); ++t) tmp[t] = (float)src[t];
+  return upload(b, tmp.data(), tmp.size() * sizeof(float), s, total);
+}
+
+}  // namespace
+
+extern "C" {
+
+int cweno_abi_version(void) { return CWENO_ABI_VERSION; }
+
+const char* cweno_last_error(void) { return g_last_error.c_str(); }
+
+const char* cweno_status_string(cweno_status st) {
+  switch (st) {
+    case CWENO_OK: return "ok";
+    case CWENO_E_ARG: return "invalid argument";
+    case CWENO_E_MESH: return "invalid mesh";
+    case CWENO_E_STENCIL: return "stencil cannot be filled";
+    case CWENO_E_RANK: return "rank-deficient least-squares system";
+    case CWENO_E_PERIODIC: return "stencil reaches too far across the periodic box";
+    case CWENO_E_NOMEM: return "out of memory";
+    case CWENO_E_BUDGET: return "memory budget exceeded";
+    case CWENO_E_HIP: return "HIP runtime error";
+    case CWENO_E_BUSY: return "busy";
+    case CWENO_E_CANCELLED: return "cancelled";
+  }
+  return "unknown status";
+}
+
+cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertices, int64_t n_cells,
+                               const int32_t* cells, int degree, const cweno_options* opt,
+                               void* hip_stream, cweno_mesh** out) {
+  if (!out) return fail(CWENO_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return fail(CWENO_E_ARG, "dim must be 2 or 3");
+  if (n_vertices <= 0 || !vertices) return fail(CWENO_E_ARG, "no vertices");
+  if (n_cells <= 0 || n_cells >= (int64_t(1) << 31) || !cells) return fail(CWENO_E_ARG, "bad cell count");
+  if (degree < 1 || degree > 4) return fail(CWENO_E_ARG, "degree must be in 1..4");
+  cweno_options o{};
+  if (opt) o = *opt;
+  std::unique_ptr<cweno_mesh> m;
+  try {
+    m.reset(new cweno_mesh());
+  } catch (const std::bad_alloc&) {
+    return fail(CWENO_E_NOMEM, "host allocation failed");
+  }
+  m->d = dim;
+  m->M = degree;
+  m->nb = cweno::n_basis(degree, dim);
+  m->nc = n_cells;
+  m->flags = o.flags;
+  m->ops = o.ops;
+  if (o.ops < CWENO_OPS_F64 || o.ops > CWENO_OPS_BOTH) return fail(CWENO_E_ARG, "bad ops");
+  if (o.sector_rule != CWENO_SECTOR_CONE && o.sector_rule != CWENO_SECTOR_FACE)
+    return fail(CWENO_E_ARG, "bad sector rule");
+  const double f = o.stencil_factor == 0.0 ? (double)dim : o.stencil_factor;
+  if (!(f > 0.0)) return fail(CWENO_E_ARG, "stencil factor must be positive");
+  m->n_e = (int)std::ceil(f * m->nb);
+  if (m->n_e < m->nb) return fail(CWENO_E_ARG, "central stencil smaller than the basis");
+  if (o.lambda0 < 0.0) {
+    double tot = 1e5 + (dim + 1);
+    m->lam[0] = 1e5 / tot;
+    for (int s = 1; s <= dim + 1; ++s) m->lam[s] = 1.0 / tot;
+  } else {
+    double l0 = o.lambda0 == 0.0 ? 0.95 : o.lambda0;
+    if (!(l0 > 0.0 && l0 < 1.0)) return fail(CWENO_E_ARG, "lambda0 must lie in (0, 1)");
+    m->lam[0] = l0;
+    for (int s = 1; s <= dim + 1; ++s) m->lam[s] = (1.0 - l0) / (dim + 1);
+  }
+  m->eps = o.eps == 0.0 ? 1e-14 : o.eps;
+  if (!(m->eps > 0.0)) return fail(CWENO_E_ARG, "eps must be positive");
+  m->r = o.r == 0 ? 4 : o.r;
+  if (m->r < 1 || m->r > 16) return fail(CWENO_E_ARG, "r must be in 1..16");
+  for (int a = 0; a < 3; ++a)
+    if (!(o.periodic[a] >= 0.0)) return fail(CWENO_E_ARG, "periodic box length must be >= 0");
+
+  try {
+    cweno::MeshInput in;
+    in.d = dim;
+    in.nv = n_vertices;
+    in.V = vertices;
+    in.nc = n_cells;
+    in.C = cells;
+    for (int a = 0; a < 3; ++a) in.box[a] = a < dim ? o.periodic[a] : 0.0;
+    cweno::Geometry g;
+    cweno::build_geometry(in, g);
+    cweno::face_adjacency(in, m->nbr);
+    cweno::Stencils st;
+    cweno::build_stencils(g, m->nbr, m->n_e, o.sector_rule, st);
+    cweno::build_operators(g, st, degree, m->op);
+    m->central.swap(st.central);
+    m->sectors.swap(st.sectors);
+  } catch (const cweno::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(CWENO_E_NOMEM, "host allocation failed during precompute");
+  } catch (const std::exception& e) {
+    return fail(CWENO_E_ARG, e.what());
+  }
+  m->G = m->op.G;
+  m->Np = m->op.Np;
+  m->n_dropped = m->op.n_dropped;
+
+  if (!(o.flags & CWENO_FLAG_HOST_ONLY)) {
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (hipGetDevice(&m->device) != hipSuccess) return fail(CWENO_E_HIP, "no HIP device");
+    const cweno::Operators& op = m->op;
+    cweno_status st;
+    if (o.ops == CWENO_OPS_F64 || o.ops == CWENO_OPS_BOTH) {
+      if ((st = upload(m->pinv64, op.pinv.data(), op.pinv.size() * 8, s, m->device_bytes))) return st;
+      if ((st = upload(m->binv64, op.binv.data(), op.binv.size() * 8, s, m->device_bytes))) return st;
+      if ((st = upload(m->sigma64, op.sigma.data(), op.sigma.size() * 8, s, m->device_bytes))) return st;
+    }
+    if (o.ops == CWENO_OPS_F32 || o.ops == CWENO_OPS_BOTH) {
+      if ((st = upload_f32(m->pinv32, op.pinv, s, m->device_bytes))) return st;
+      if ((st = upload_f32(m->binv32, op.binv, s, m->device_bytes))) return st;
+      if ((st = upload_f32(m->sigma32, op.sigma, s, m->device_bytes))) return st;
+    }
+    if ((st = upload(m->gidx, op.gidx.data(), op.gidx.size() * 4, s, m->device_bytes))) return st;
+    if ((st = upload(m->secpos, op.secpos.data(), op.secpos.size(), s, m->device_bytes))) return st;
+    if ((st = upload(m->mask, op.mask.data(), op.mask.size(), s, m->device_bytes))) return st;
+    // the device holds the operators now; keep only what the host-side dumps need
+    std::vector<double>().swap(m->op.pinv);
+    std::vector<double>().swap(m->op.binv);
+    std::vector<int32_t>().swap(m->op.gidx);
+    std::vector<uint8_t>().swap(m->op.secpos);
+  }
+  *out = m.release();
+  return CWENO_OK;
+}
+
+cweno_status cweno_mesh_destroy(cweno_mesh* mesh) {
+  delete mesh;
+  return CWENO_OK;
+}
+
+cweno_status cweno_mesh_info(const cweno_mesh* m, int64_t* n_cells, int* n_basis, int* n_e, int* gather_len,
+                             int64_t* device_bytes, int64_t* n_dropped) {
+  if (!m) return fail(CWENO_E_ARG, "mesh is NULL");
+  if (n_cells) *n_cells = m->nc;
+  if (n_basis) *n_basis = m->nb;
+  if (n_e) *n_e = m->n_e;
+  if (gather_len) *gather_len = m->G;
+  if (device_bytes) *device_bytes = m->device_bytes;
+  if (n_dropped) *n_dropped = m->n_dropped;
+  return CWENO_OK;
+}
+
+cweno_status cweno_mesh_tables(const cweno_mesh* m, int32_t* face_nbr, int32_t* stencil, int32_t* sectors) {
+  if (!m) return fail(CWENO_E_ARG, "mesh is NULL");
+  if (face_nbr) std::memcpy(face_nbr, m->nbr.data(), m->nbr.size() * 4);
+  if (stencil) std::memcpy(stencil, m->central.data(), m->central.size() * 4);
+  if (sectors) std::memcpy(sectors, m->sectors.data(), m->sectors.size() * 4);
+  return CWENO_OK;
+}
+
+cweno_status cweno_mesh_operators(const cweno_mesh* m, int64_t cell, double* pinv, double* binv, double* sigma) {
+  if (!m) return fail(CWENO_E_ARG, "mesh is NULL");
+  if (cell < 0 || cell >= m->nc) return fail(CWENO_E_ARG, "cell out of range");
+  const cweno::Operators& op = m->op;
+  const size_t Np = (size_t)m->Np;
+  if ((pinv || binv) && op.pinv.empty())
+    return fail(CWENO_E_ARG, "per-cell operators are kept on the host only for host-only meshes");
+  const int NE1 = m->n_e - 1, NL = m->nb - 1, d = m->d;
+  if (pinv)
+    for (int t = 0; t < NL * NE1; ++t) pinv[t] = op.pinv[(size_t)t * Np + cell];
+  if (binv)
+    for (int t = 0; t < (d + 1) * d * d; ++t) binv[t] = op.binv[(size_t)t * Np + cell];
+  if (sigma) std::memcpy(sigma, op.sigma.data(), op.sigma.size() * 8);
+  return CWENO_OK;
+}
+
+cweno_status cweno_reconstruct(const cweno_mesh* m, int n_vars, cweno_dtype dtype, const void* q, void* coeffs,
+                               void* sigma, void* omega, void* hip_stream) {
+  if (!m) return fail(CWENO_E_ARG, "mesh is NULL");
+  if (n_vars < 1) return fail(CWENO_E_ARG, "n_vars must be >= 1");
+  if (!q || !coeffs) return fail(CWENO_E_ARG, "q and coeffs must be device pointers");
+  if (m->flags & CWENO_FLAG_HOST_ONLY) return fail(CWENO_E_ARG, "mesh was built host-only");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const bool f32 = dtype == CWENO_F32;
+  if (dtype != CWENO_F64 && dtype != CWENO_F32) return fail(CWENO_E_ARG, "bad dtype");
+  if ((f32 && !m->pinv32.p) || (!f32 && !m->pinv64.p))
+    return fail(CWENO_E_ARG, "the mesh holds no operators of this precision");
+  int v0 = 0;
+  while (v0 < n_vars) {
+    const int vb = cweno::pick_vb(m->d, m->M, n_vars - v0, f32);
+    hipError_t e;
+    if (f32) {
+      cweno::KParams<float> p{};
+      p.q = (const float*)q;
+      p.out = (float*)coeffs;
+      p.sig = (float*)sigma;
+      p.om = (float*)omega;
+      p.pinv = (const float*)m->pinv32.p;
+      p.binv = (const float*)m->binv32.p;
+      p.sigma = (const float*)m->sigma32.p;
+      p.gidx = (const int32_t*)m->gidx.p;
+      p.secpos = (const uint8_t*)m->secpos.p;
+      p.mask = (const uint8_t*)m->mask.p;
+      p.nc = m->nc;
+      p.Np = m->Np;
+      p.NE1 = m->n_e - 1;
+      p.v0 = v0;
+      p.r = m->r;
+      p.sigma0_popt = (m->flags & CWENO_FLAG_SIGMA0_POPT) ? 1 : 0;
+      p.linear_w = (m->flags & CWENO_FLAG_LINEAR_WEIGHTS) ? 1 : 0;
+      for (int t = 0; t < 5; ++t) p.lam[t] = (float)m->lam[t];
+      p.eps = (float)m->eps;
+      e = m->d == 2 ? cweno::launch_f32_d2(m->M, vb, p, s) : cweno::launch_f32_d3(m->M, vb, p, s);
+    } else {
+      cweno::KParams<double> p{};
+      p.q = (const double*)q;
+      p.out = (double*)coeffs;
+      p.sig = (double*)sigma;
+      p.om = (double*)omega;
+      p.pinv = (const double*)m->pinv64.p;
+      p.binv = (const double*)m->binv64.p;
+      p.sigma = (const double*)m->sigma64.p;
+      p.gidx = (const int32_t*)m->gidx.p;
+      p.secpos = (const uint8_t*)m->secpos.p;
+      p.mask = (const uint8_t*)m->mask.p;
+      p.nc = m->nc;
+      p.Np = m->Np;
+      p.NE1 = m->n_e - 1;
+      p.v0 = v0;
+      p.r = m->r;
+      p.sigma0_popt = (m->flags & CWENO_FLAG_SIGMA0_POPT) ? 1 : 0;
+      p.linear_w = (m->flags & CWENO_FLAG_LINEAR_WEIGHTS) ? 1 : 0;
+      for (int t = 0; t < 5; ++t) p.lam[t] = m->lam[t];
+      p.eps = m->eps;
+      e = m->d == 2 ? cweno::launch_f64_d2(m->M, vb, p, s) : cweno::launch_f64_d3(m->M, vb, p, s);
+    }
+    if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    v0 += vb;
+  }
+  return CWENO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+"""GPU parity: the HIP reconstruction (through the C ABI) against the oracle.
+
+FP64 bar: data-scaled error <= 1e-12 (each coefficient difference divided by
+the largest |Q| of the cell's central stencil), indicators to 1e-9 relative,
+weights to 1e-9 absolute; coefficient 0 is a bitwise copy of the input.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import data_scaled_error, run_library, torch_cuda
+from oracle import CwenoOracle, Options
+from synthetic import kuhn_tet_mesh, tri_mesh, workload_fields
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _lib():
+    import paper_1612_09335_amd as C
+    return C
+
+
+def _check_f64(m, M, Q, factor=0.0, cells=None, **opts):
+    torch = torch_cuda()
+    C = _lib()
+    lib_opts = {k: v for k, v in opts.items() if k in ("sector_rule", "r", "eps")}
+    if "lambda0" in opts:
+        lib_opts["lambda0"] = -1.0 if opts["lambda0"] == "paper" else opts["lambda0"]
+    if opts.get("sigma0_from") == "popt":
+        lib_opts["sigma0_popt"] = True
+    if opts.get("linear_weights"):
+        lib_opts["linear_weights"] = True
+    print(f"[gpu parity] {m.name} M={M} nv={Q.shape[0]} cells={m.n_cells} opts={opts}", flush=True)
+    lm = C.Mesh(m.vertices, m.cells, M, periodic=m.box, stencil_factor=factor, **lib_opts)
+    res = run_library(torch, lm, Q, torch.float64)
+    assert np.array_equal(res["coeffs"][:, 0, :].view(np.int64), Q.view(np.int64))
+    o = CwenoOracle(m.vertices, m.cells, m.box, Options(degree=M, stencil_factor=factor, **opts))
+    idx = np.arange(m.n_cells) if cells is None else np.asarray(cells)
+    ref = o.reconstruct(Q, cells=idx)
+    st = lm.tables()["stencil"][idx]
+    err = data_scaled_error(res["coeffs"][:, :, idx], ref["coeffs"], Q, st)
+    print(f"[gpu parity]   data-scaled coefficient error {err:.3e}", flush=True)
+    assert err <= TOL64
+    sg, om = res["sigma"][:, :, idx], res["omega"][:, :, idx]
+    scale2 = (np.abs(Q[:, st]).max(axis=2) ** 2)[:, None, :]
+    assert np.all(np.abs(sg - ref["sigma"]) <= 1e-9 * np.abs(ref["sigma"]) + 1e-20 * scale2)
+    assert np.abs(om - ref["omega"]).max() <= 1e-9
+    return lm, res
+
+
+def test_cfg1_full_mesh_f64():
+    """2-D M=2, 64x64x2 jittered periodic triangles, n_e = 9, Euler + Sod circle."""
+    m = tri_mesh(64, 0.15, 16120934)
+    Q = workload_fields(m, "euler2d_sod", 16120934)
+    _check_f64(m, 2, Q, factor=1.5)
+
+
+@pytest.mark.parametrize("case", ["tri13_M3_nv7", "kuhn5_M2_nv3", "tri12_M4_nv2", "kuhn6_M1_nv5",
+                                  "tri10_M3_bounded", "kuhn4_M2_bounded"])
+def test_small_meshes_f64(case):
+    rng = np.random.default_rng(abs(hash(case)) % 2**32)
+    if case == "tri13_M3_nv7":
+        m, M, nv = tri_mesh(13, 0.15, 1), 3, 7
+    elif case == "kuhn5_M2_nv3":
+        m, M, nv = kuhn_tet_mesh(5, 0.1, 2), 2, 3
+    elif case == "tri12_M4_nv2":
+        m, M, nv = tri_mesh(12, 0.15, 3), 4, 2
+    elif case == "kuhn6_M1_nv5":
+        m, M, nv = kuhn_tet_mesh(6, 0.1, 4), 1, 5
+    elif case == "tri10_M3_bounded":
+        m, M, nv = tri_mesh(10, 0.15, 5, periodic=False), 3, 3
+    else:
+        m, M, nv = kuhn_tet_mesh(4, 0.1, 6, periodic=False), 2, 4
+    Q = rng.normal(size=(nv, m.n_cells)) + 4.0 * (rng.random((1, m.n_cells)) < 0.25)
+    _check_f64(m, M, Q)
+
+
+@pytest.mark.parametrize("opt", [dict(sector_rule="face"), dict(lambda0="paper"), dict(sigma0_from="popt"),
+                                 dict(linear_weights=True), dict(r=2, eps=1e-6), dict(lambda0=0.5)])
+def test_options_f64(opt):
+    m = tri_mesh(11, 0.15, 21)
+    rng = np.random.default_rng(22)
+    Q = rng.normal(size=(2, m.n_cells)) + 3.0 * (rng.random((1, m.n_cells)) < 0.3)
+    _check_f64(m, 3, Q, **opt)
+
+
+def test_deterministic_and_stream_ordered():
+    torch = torch_cuda()
+    C = _lib()
+    m = tri_mesh(32, 0.15, 31)
+    Q = workload_fields(m, "mhd2d", 31)
+    lm = C.Mesh(m.vertices, m.cells, 3, periodic=m.box)
+    a = run_library(torch, lm, Q, torch.float64)["coeffs"]
+    b = run_library(torch, lm, Q, torch.float64)["coeffs"]
+    assert np.array_equal(a.view(np.int64), b.view(np.int64))
