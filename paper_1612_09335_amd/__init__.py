@@ -44,6 +44,13 @@ class _Options(ctypes.Structure):
 
 
 def _load():
+    # torch bundles its own HIP runtime with the same soname as ROCm's; loading
+    # torch first makes the library bind to that runtime, so device pointers
+    # and streams are shared by one runtime instance in the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1612_09335_amd.build`")
     lib = ctypes.CDLL(LIB_PATH)
