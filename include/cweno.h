@@ -196,6 +196,37 @@ cweno_status cweno_reconstruct(const cweno_mesh* mesh, int n_vars, cweno_dtype d
                                const void* q, void* coeffs, void* sigma, void* omega,
                                void* hip_stream);
 
+/*
+ * Kernel variants and their autotuner.
+ *
+ * The reconstruction kernel exists in several variants (cweno_num_variants()):
+ * variant k assigns RS lanes of a wavefront to each cell, each lane owning
+ * every RS-th row of the P_opt operator, and walks the stencil in chunks of
+ * KC entries.  All variants compute the same values (the per-lane sums run
+ * over the stencil in the same order); they differ only in speed.  A mesh
+ * keeps one variant per (precision, variable block); variables are processed
+ * in blocks of at most 9 (the block sizes instantiated for the mesh's degree
+ * and dimension), each block reading the operators once.
+ *
+ * cweno_mesh_set_variant  choose variant `variant` for blocks of `vb` variables
+ *                         (CWENO_E_ARG if that combination is not instantiated)
+ * cweno_mesh_get_variant  report the current choice (variant index, RS, KC)
+ * cweno_mesh_tune         time every instantiated variant for each block that a
+ *                         cweno_reconstruct of n_vars variables would launch,
+ *                         using the caller's device buffers q [n_vars][n_cells]
+ *                         and coeffs [n_vars][n_basis][n_cells] (coeffs is
+ *                         overwritten), `repeats` timed launches per variant on
+ *                         hip_stream, and keep the fastest.  Blocking: it
+ *                         synchronises the stream.  *best_ms (may be NULL)
+ *                         receives the tuned time of one full reconstruction.
+ */
+int cweno_num_variants(void);
+cweno_status cweno_mesh_set_variant(cweno_mesh* mesh, cweno_dtype dtype, int vb, int variant);
+cweno_status cweno_mesh_get_variant(const cweno_mesh* mesh, cweno_dtype dtype, int vb, int* variant, int* rs,
+                                    int* kc);
+cweno_status cweno_mesh_tune(cweno_mesh* mesh, int n_vars, cweno_dtype dtype, const void* q, void* coeffs,
+                             int repeats, void* hip_stream, double* best_ms);
+
 const char* cweno_status_string(cweno_status status);
 const char* cweno_last_error(void);
 int cweno_abi_version(void);

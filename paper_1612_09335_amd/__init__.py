@@ -27,7 +27,8 @@ STATUS = {0: "CWENO_OK", -1: "CWENO_E_ARG", -2: "CWENO_E_MESH", -3: "CWENO_E_STE
 
 SYMBOLS = ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_mesh_tables",
            "cweno_mesh_operators", "cweno_reconstruct", "cweno_status_string", "cweno_last_error",
-           "cweno_abi_version")
+           "cweno_abi_version", "cweno_num_variants", "cweno_mesh_set_variant", "cweno_mesh_get_variant",
+           "cweno_mesh_tune")
 
 
 class CwenoError(RuntimeError):
@@ -52,7 +53,7 @@ def _load():
     except ImportError:
         pass
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1612_09335_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1612_09335_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     vp, i64, i32p = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)
     lib.cweno_mesh_create.argtypes = [ctypes.c_int, i64, vp, i64, vp, ctypes.c_int, ctypes.POINTER(_Options),
@@ -64,11 +65,17 @@ def _load():
     lib.cweno_mesh_tables.argtypes = [vp, vp, vp, vp]
     lib.cweno_mesh_operators.argtypes = [vp, i64, vp, vp, vp]
     lib.cweno_reconstruct.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
+    lib.cweno_mesh_set_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.cweno_mesh_get_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.cweno_mesh_tune.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp,
+                                    ctypes.POINTER(ctypes.c_double)]
     lib.cweno_status_string.argtypes = [ctypes.c_int]
     lib.cweno_status_string.restype = ctypes.c_char_p
     lib.cweno_last_error.restype = ctypes.c_char_p
     for name in ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_mesh_tables",
-                 "cweno_mesh_operators", "cweno_reconstruct"):
+                 "cweno_mesh_operators", "cweno_reconstruct", "cweno_mesh_set_variant",
+                 "cweno_mesh_get_variant", "cweno_mesh_tune", "cweno_num_variants"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -178,6 +185,34 @@ class Mesh:
                                      None if sigma is None else sigma.data_ptr(),
                                      None if omega is None else omega.data_ptr(), _stream_ptr(stream)))
         return out
+
+
+    # ---------------------------------------------------------------- variants
+    def set_variant(self, dtype: str, vb: int, variant: int):
+        _check(lib.cweno_mesh_set_variant(self._h, {"f64": F64, "f32": F32}[dtype], vb, variant))
+
+    def get_variant(self, dtype: str, vb: int):
+        k, rs, kc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib.cweno_mesh_get_variant(self._h, {"f64": F64, "f32": F32}[dtype], vb, ctypes.byref(k),
+                                          ctypes.byref(rs), ctypes.byref(kc)))
+        return k.value, rs.value, kc.value
+
+    def tune(self, q, out=None, repeats: int = 5, stream=None) -> float:
+        """cweno_mesh_tune on the given averages; returns the tuned time (ms)."""
+        import torch
+        dt = {torch.float64: F64, torch.float32: F32}[q.dtype]
+        if out is None:
+            out = torch.empty((q.shape[0], self.n_basis, self.n_cells), dtype=q.dtype, device=q.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(q.device)
+        ms = ctypes.c_double()
+        _check(lib.cweno_mesh_tune(self._h, q.shape[0], dt, q.data_ptr(), out.data_ptr(), repeats,
+                                   _stream_ptr(stream), ctypes.byref(ms)))
+        return ms.value
+
+
+def num_variants() -> int:
+    return lib.cweno_num_variants()
 
 
 def _stream_ptr(stream):

@@ -1,6 +1,7 @@
 """Build ``libcweno.so`` in-tree: host precompute (g++) + gfx950 kernels (hipcc).
 
-Usage: ``python -m paper_1612_09335_amd.build`` (or ``build()`` from Python).
+Usage: ``python paper_1612_09335_amd/build.py`` (run by path: importing the
+package loads the library it builds), or ``__graft_entry__.build()``.
 Every call recompiles every source.
 """
 from __future__ import annotations
@@ -22,7 +23,9 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["host_geometry.cpp", "host_basis.cpp", "host_operators.cpp"]
-HIP_SOURCES = ["abi.hip", "kernels_f64_d2.hip", "kernels_f64_d3.hip", "kernels_f32_d2.hip", "kernels_f32_d3.hip"]
+HIP_SOURCES = ["abi.hip"]
+# kernels.hip is compiled once per (precision, dimension, degree)
+KERNEL_UNITS = [(tn, d, m) for tn in ("f64", "f32") for d in (2, 3) for m in (1, 2, 3, 4)]
 
 # Integer tables depend on exact floating-point comparisons: no contraction.
 HOST_FLAGS = ["-std=c++17", "-O2", "-fPIC", "-pthread", "-ffp-contract=off", "-Wall", "-Wextra",
@@ -54,6 +57,11 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         cmds.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    for tn, d, m in KERNEL_UNITS:
+        obj = os.path.join(BUILD, f"kernels_{tn}_d{d}_m{m}.o")
+        cmds.append([HIPCC, *HIP_FLAGS, f"-DCWENO_TN={tn}", f"-DCWENO_D={d}", f"-DCWENO_M={m}", "-c",
+                     os.path.join(CSRC, "kernels.hip"), "-o", obj])
         objs.append(obj)
     jobs = jobs or min(16, os.cpu_count() or 4, len(cmds))
     with cf.ThreadPoolExecutor(jobs) as ex:

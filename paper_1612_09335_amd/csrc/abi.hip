@@ -45,6 +45,8 @@ struct cweno_mesh {
   int device = -1;
   DevBuf pinv64, binv64, sigma64, pinv32, binv32, sigma32, gidx, secpos, mask;
   int64_t device_bytes = 0;
+  // kernel variant (index into cweno::kVariants) per [precision][variable block]
+  int variant[2][10];
 
   ~cweno_mesh() {
     for (DevBuf* b : {&pinv64, &binv64, &sigma64, &pinv32, &binv32, &sigma32, &gidx, &secpos, &mask})
@@ -75,6 +77,65 @@ cweno_status upload_f32(DevBuf& b, const std::vector<double>& src, hipStream_t s
   std::vector<float> tmp(src.size());
   for (size_t t = 0; t < src.size(); ++t) tmp[t] = (float)src[t];
   return upload(b, tmp.data(), tmp.size() * sizeof(float), s, total);
+}
+
+// Default variant: the candidate order below, first one instantiated for the block.
+int default_variant(int d, int M, int vb, bool f32) {
+  const int order[] = {4, 2, 5, 3, 1, 0};   // (4,2) (2,2) (4,4) (2,4) (1,2) (1,1)
+  for (int k : order)
+    if (cweno::vb_allowed(d, M, vb, cweno::kVariants[k].rs, f32)) return k;
+  return -1;
+}
+
+template <typename T>
+cweno::KParams<T> make_params(const cweno_mesh* m, const void* q, void* coeffs, void* sigma, void* omega, int v0) {
+  const bool f32 = sizeof(T) == 4;
+  cweno::KParams<T> p{};
+  p.q = (const T*)q;
+  p.out = (T*)coeffs;
+  p.sig = (T*)sigma;
+  p.om = (T*)omega;
+  p.pinv = (const T*)(f32 ? m->pinv32.p : m->pinv64.p);
+  p.binv = (const T*)(f32 ? m->binv32.p : m->binv64.p);
+  p.sigma = (const T*)(f32 ? m->sigma32.p : m->sigma64.p);
+  p.gidx = (const int32_t*)m->gidx.p;
+  p.secpos = (const uint8_t*)m->secpos.p;
+  p.mask = (const uint8_t*)m->mask.p;
+  p.nc = m->nc;
+  p.Np = m->Np;
+  p.NE1 = m->n_e - 1;
+  p.v0 = v0;
+  p.r = m->r;
+  p.sigma0_popt = (m->flags & CWENO_FLAG_SIGMA0_POPT) ? 1 : 0;
+  p.linear_w = (m->flags & CWENO_FLAG_LINEAR_WEIGHTS) ? 1 : 0;
+  for (int t = 0; t < 5; ++t) p.lam[t] = (T)m->lam[t];
+  p.eps = (T)m->eps;
+  return p;
+}
+
+// Launch one variable block [v0, v0+vb) with variant index k.
+hipError_t launch_block(const cweno_mesh* m, bool f32, const void* q, void* coeffs, void* sigma, void* omega,
+                        int v0, int vb, int k, hipStream_t s) {
+  const cweno::Variant& V = cweno::kVariants[k];
+  if (f32)
+    return cweno::launch<float>(m->d, m->M, make_params<float>(m, q, coeffs, sigma, omega, v0), vb, V.rs, V.kc, s);
+  return cweno::launch<double>(m->d, m->M, make_params<double>(m, q, coeffs, sigma, omega, v0), vb, V.rs, V.kc, s);
+}
+
+cweno_status check_reconstruct_args(const cweno_mesh* m, int n_vars, cweno_dtype dtype, const void* q,
+                                    const void* coeffs) {
+  if (!m) return fail(CWENO_E_ARG, "mesh is NULL");
+  if (n_vars < 1) return fail(CWENO_E_ARG, "n_vars must be >= 1");
+  if (!q || !coeffs) return fail(CWENO_E_ARG, "q and coeffs must be device pointers");
+  if (m->flags & CWENO_FLAG_HOST_ONLY) return fail(CWENO_E_ARG, "mesh was built host-only");
+  if (dtype != CWENO_F64 && dtype != CWENO_F32) return fail(CWENO_E_ARG, "bad dtype");
+  const bool f32 = dtype == CWENO_F32;
+  if ((f32 && !m->pinv32.p) || (!f32 && !m->pinv64.p))
+    return fail(CWENO_E_ARG, "the mesh holds no operators of this precision");
+  // neighbour averages are gathered with 32-bit byte offsets within one variable
+  if ((uint64_t)m->nc * (f32 ? 4u : 8u) >= (uint64_t(1) << 32))
+    return fail(CWENO_E_ARG, "too many cells for 32-bit offsets");
+  return CWENO_OK;
 }
 
 }  // namespace
@@ -174,7 +235,12 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
   }
   m->G = m->op.G;
   m->Np = m->op.Np;
+  // the kernels address an operator row block and the averages with 32-bit byte offsets
+  if ((uint64_t)(m->nb - 1) * (uint64_t)m->Np * 8u >= (uint64_t(1) << 32))
+    return fail(CWENO_E_ARG, "mesh too large for one device operator block (split it)");
   m->n_dropped = m->op.n_dropped;
+  for (int t = 0; t < 2; ++t)
+    for (int vb = 0; vb < 10; ++vb) m->variant[t][vb] = vb == 0 ? -1 : default_variant(dim, degree, vb, t == 1);
 
   if (!(o.flags & CWENO_FLAG_HOST_ONLY)) {
     hipStream_t s = (hipStream_t)hip_stream;
@@ -238,7 +304,8 @@ cweno_status cweno_mesh_operators(const cweno_mesh* m, int64_t cell, double* pin
     return fail(CWENO_E_ARG, "per-cell operators are kept on the host only for host-only meshes");
   const int NE1 = m->n_e - 1, NL = m->nb - 1, d = m->d;
   if (pinv)
-    for (int t = 0; t < NL * NE1; ++t) pinv[t] = op.pinv[(size_t)t * Np + cell];
+    for (int l = 0; l < NL; ++l)
+      for (int k = 0; k < NE1; ++k) pinv[l * NE1 + k] = op.pinv[((size_t)k * NL + l) * Np + cell];
   if (binv)
     for (int t = 0; t < (d + 1) * d * d; ++t) binv[t] = op.binv[(size_t)t * Np + cell];
   if (sigma) std::memcpy(sigma, op.sigma.data(), op.sigma.size() * 8);
@@ -247,68 +314,90 @@ cweno_status cweno_mesh_operators(const cweno_mesh* m, int64_t cell, double* pin
 
 cweno_status cweno_reconstruct(const cweno_mesh* m, int n_vars, cweno_dtype dtype, const void* q, void* coeffs,
                                void* sigma, void* omega, void* hip_stream) {
-  if (!m) return fail(CWENO_E_ARG, "mesh is NULL");
-  if (n_vars < 1) return fail(CWENO_E_ARG, "n_vars must be >= 1");
-  if (!q || !coeffs) return fail(CWENO_E_ARG, "q and coeffs must be device pointers");
-  if (m->flags & CWENO_FLAG_HOST_ONLY) return fail(CWENO_E_ARG, "mesh was built host-only");
+  cweno_status st = check_reconstruct_args(m, n_vars, dtype, q, coeffs);
+  if (st) return st;
   hipStream_t s = (hipStream_t)hip_stream;
   const bool f32 = dtype == CWENO_F32;
-  if (dtype != CWENO_F64 && dtype != CWENO_F32) return fail(CWENO_E_ARG, "bad dtype");
-  if ((f32 && !m->pinv32.p) || (!f32 && !m->pinv64.p))
-    return fail(CWENO_E_ARG, "the mesh holds no operators of this precision");
-  int v0 = 0;
-  while (v0 < n_vars) {
+  for (int v0 = 0; v0 < n_vars;) {
     const int vb = cweno::pick_vb(m->d, m->M, n_vars - v0, f32);
-    hipError_t e;
-    if (f32) {
-      cweno::KParams<float> p{};
-      p.q = (const float*)q;
-      p.out = (float*)coeffs;
-      p.sig = (float*)sigma;
-      p.om = (float*)omega;
-      p.pinv = (const float*)m->pinv32.p;
-      p.binv = (const float*)m->binv32.p;
-      p.sigma = (const float*)m->sigma32.p;
-      p.gidx = (const int32_t*)m->gidx.p;
-      p.secpos = (const uint8_t*)m->secpos.p;
-      p.mask = (const uint8_t*)m->mask.p;
-      p.nc = m->nc;
-      p.Np = m->Np;
-      p.NE1 = m->n_e - 1;
-      p.v0 = v0;
-      p.r = m->r;
-      p.sigma0_popt = (m->flags & CWENO_FLAG_SIGMA0_POPT) ? 1 : 0;
-      p.linear_w = (m->flags & CWENO_FLAG_LINEAR_WEIGHTS) ? 1 : 0;
-      for (int t = 0; t < 5; ++t) p.lam[t] = (float)m->lam[t];
-      p.eps = (float)m->eps;
-      e = m->d == 2 ? cweno::launch_f32_d2(m->M, vb, p, s) : cweno::launch_f32_d3(m->M, vb, p, s);
-    } else {
-      cweno::KParams<double> p{};
-      p.q = (const double*)q;
-      p.out = (double*)coeffs;
-      p.sig = (double*)sigma;
-      p.om = (double*)omega;
-      p.pinv = (const double*)m->pinv64.p;
-      p.binv = (const double*)m->binv64.p;
-      p.sigma = (const double*)m->sigma64.p;
-      p.gidx = (const int32_t*)m->gidx.p;
-      p.secpos = (const uint8_t*)m->secpos.p;
-      p.mask = (const uint8_t*)m->mask.p;
-      p.nc = m->nc;
-      p.Np = m->Np;
-      p.NE1 = m->n_e - 1;
-      p.v0 = v0;
-      p.r = m->r;
-      p.sigma0_popt = (m->flags & CWENO_FLAG_SIGMA0_POPT) ? 1 : 0;
-      p.linear_w = (m->flags & CWENO_FLAG_LINEAR_WEIGHTS) ? 1 : 0;
-      for (int t = 0; t < 5; ++t) p.lam[t] = m->lam[t];
-      p.eps = m->eps;
-      e = m->d == 2 ? cweno::launch_f64_d2(m->M, vb, p, s) : cweno::launch_f64_d3(m->M, vb, p, s);
-    }
+    const int k = m->variant[f32][vb];
+    hipError_t e = launch_block(m, f32, q, coeffs, sigma, omega, v0, vb, k, s);
     if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     v0 += vb;
   }
   return CWENO_OK;
+}
+
+cweno_status cweno_mesh_set_variant(cweno_mesh* m, cweno_dtype dtype, int vb, int variant) {
+  if (!m) return fail(CWENO_E_ARG, "mesh is NULL");
+  if (dtype != CWENO_F64 && dtype != CWENO_F32) return fail(CWENO_E_ARG, "bad dtype");
+  if (vb < 1 || vb > 9) return fail(CWENO_E_ARG, "variable block out of range");
+  if (variant < 0 || variant >= cweno::kNumVariants) return fail(CWENO_E_ARG, "variant out of range");
+  if (!cweno::vb_allowed(m->d, m->M, vb, cweno::kVariants[variant].rs, dtype == CWENO_F32))
+    return fail(CWENO_E_ARG, "variant not instantiated for this block");
+  m->variant[dtype == CWENO_F32][vb] = variant;
+  return CWENO_OK;
+}
+
+cweno_status cweno_mesh_get_variant(const cweno_mesh* m, cweno_dtype dtype, int vb, int* variant, int* rs,
+                                    int* kc) {
+  if (!m) return fail(CWENO_E_ARG, "mesh is NULL");
+  if (dtype != CWENO_F64 && dtype != CWENO_F32) return fail(CWENO_E_ARG, "bad dtype");
+  if (vb < 1 || vb > 9) return fail(CWENO_E_ARG, "variable block out of range");
+  const int k = m->variant[dtype == CWENO_F32][vb];
+  if (variant) *variant = k;
+  if (rs) *rs = k >= 0 ? cweno::kVariants[k].rs : 0;
+  if (kc) *kc = k >= 0 ? cweno::kVariants[k].kc : 0;
+  return CWENO_OK;
+}
+
+int cweno_num_variants(void) { return cweno::kNumVariants; }
+
+cweno_status cweno_mesh_tune(cweno_mesh* m, int n_vars, cweno_dtype dtype, const void* q, void* coeffs,
+                             int repeats, void* hip_stream, double* best_ms) {
+  cweno_status st = check_reconstruct_args(m, n_vars, dtype, q, coeffs);
+  if (st) return st;
+  if (repeats < 1) return fail(CWENO_E_ARG, "repeats must be >= 1");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const bool f32 = dtype == CWENO_F32;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(CWENO_E_HIP, "hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(CWENO_E_HIP, "hipEventCreate failed");
+  }
+  double total = 0.0;
+  st = CWENO_OK;
+  for (int v0 = 0; v0 < n_vars && st == CWENO_OK;) {
+    const int vb = cweno::pick_vb(m->d, m->M, n_vars - v0, f32);
+    float best = 0.0f;
+    int best_k = -1;
+    for (int k = 0; k < cweno::kNumVariants && st == CWENO_OK; ++k) {
+      if (!cweno::vb_allowed(m->d, m->M, vb, cweno::kVariants[k].rs, f32)) continue;
+      hipError_t e = launch_block(m, f32, q, coeffs, nullptr, nullptr, v0, vb, k, s);   // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int t = 0; t < repeats && e == hipSuccess; ++t)
+        e = launch_block(m, f32, q, coeffs, nullptr, nullptr, v0, vb, k, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = fail(CWENO_E_HIP, std::string("tuning launch failed: ") + hipGetErrorString(e));
+        break;
+      }
+      if (best_k < 0 || ms < best) { best = ms; best_k = k; }
+    }
+    if (st == CWENO_OK) {
+      m->variant[f32][vb] = best_k;
+      total += best / repeats;
+    }
+    v0 += vb;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == CWENO_OK && best_ms) *best_ms = total;
+  return st;
 }
 
 }  // extern "C"

@@ -7,25 +7,55 @@
 
 namespace cweno {
 
-// Variable-block sizes that are instantiated.  A block of VB variables keeps
-// (n_basis-1)*VB accumulators per thread; blocks whose accumulators would not
-// fit the register budget (100 doubles / 200 floats) are not instantiated.
-__host__ __device__ constexpr bool vb_allowed(int D, int M, int VB, bool f32) {
+// Kernel variants: RS lanes per cell, KC stencil entries per chunk.
+struct Variant { int rs, kc; };
+constexpr Variant kVariants[] = {{1, 1}, {1, 2}, {2, 2}, {2, 4}, {4, 2}, {4, 4}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+// Variable-block sizes that are instantiated.  A lane keeps
+// ceil((n_basis-1)/RS) * VB accumulators; combinations whose accumulators
+// exceed the register budget (100 doubles / 200 floats) or whose row exchange
+// exceeds the 160 KiB of LDS a workgroup may use are not instantiated.
+constexpr int kMaxLds = 160 * 1024;
+__host__ __device__ constexpr bool vb_allowed(int D, int M, int VB, int RS, bool f32) {
   return (VB == 1 || VB == 2 || VB == 3 || VB == 4 || VB == 5 || VB == 9) &&
-         (nbasis_c(M, D) - 1) * VB <= (f32 ? 200 : 100);
+         ceil_div(nbasis_c(M, D) - 1, RS) * VB <= (f32 ? 200 : 100) &&
+         (RS == 1 ? 0 : (kThreads / RS) * (nbasis_c(M, D) - 1) * VB * (f32 ? 4 : 8)) <= kMaxLds;
 }
 
-// Largest instantiated block size not above n.
+// Largest block size not above n that some variant instantiates.
 inline int pick_vb(int D, int M, int n, bool f32) {
   const int cand[] = {9, 5, 4, 3, 2, 1};
   for (int vb : cand)
-    if (vb <= n && vb_allowed(D, M, vb, f32)) return vb;
+    if (vb <= n)
+      for (const Variant& v : kVariants)
+        if (vb_allowed(D, M, vb, v.rs, f32)) return vb;
   return 1;
 }
 
-hipError_t launch_f64_d2(int M, int VB, const KParams<double>& p, hipStream_t s);
-hipError_t launch_f64_d3(int M, int VB, const KParams<double>& p, hipStream_t s);
-hipError_t launch_f32_d2(int M, int VB, const KParams<float>& p, hipStream_t s);
-hipError_t launch_f32_d3(int M, int VB, const KParams<float>& p, hipStream_t s);
+#define CWENO_DECLARE(TN, T, D, M) \
+  hipError_t launch_##TN##_d##D##_m##M(const KParams<T>& p, int vb, int rs, int kc, hipStream_t s);
+#define CWENO_DECLARE_T(TN, T) \
+  CWENO_DECLARE(TN, T, 2, 1) CWENO_DECLARE(TN, T, 2, 2) CWENO_DECLARE(TN, T, 2, 3) CWENO_DECLARE(TN, T, 2, 4) \
+  CWENO_DECLARE(TN, T, 3, 1) CWENO_DECLARE(TN, T, 3, 2) CWENO_DECLARE(TN, T, 3, 3) CWENO_DECLARE(TN, T, 3, 4)
+CWENO_DECLARE_T(f64, double)
+CWENO_DECLARE_T(f32, float)
+#undef CWENO_DECLARE_T
+#undef CWENO_DECLARE
+
+template <typename T>
+inline hipError_t launch(int D, int M, const KParams<T>& p, int vb, int rs, int kc, hipStream_t s) {
+#define CWENO_CASE(TN, DD, MM) \
+  if (D == DD && M == MM) return launch_##TN##_d##DD##_m##MM(p, vb, rs, kc, s);
+  if constexpr (sizeof(T) == 8) {
+    CWENO_CASE(f64, 2, 1) CWENO_CASE(f64, 2, 2) CWENO_CASE(f64, 2, 3) CWENO_CASE(f64, 2, 4)
+    CWENO_CASE(f64, 3, 1) CWENO_CASE(f64, 3, 2) CWENO_CASE(f64, 3, 3) CWENO_CASE(f64, 3, 4)
+  } else {
+    CWENO_CASE(f32, 2, 1) CWENO_CASE(f32, 2, 2) CWENO_CASE(f32, 2, 3) CWENO_CASE(f32, 2, 4)
+    CWENO_CASE(f32, 3, 1) CWENO_CASE(f32, 3, 2) CWENO_CASE(f32, 3, 3) CWENO_CASE(f32, 3, 4)
+  }
+#undef CWENO_CASE
+  return hipErrorInvalidValue;
+}
 
 }  // namespace cweno

@@ -77,7 +77,7 @@ struct Stencils {
 struct Operators {
   int d = 2, M = 1, nb = 0, n_e = 0, G = 0;
   int64_t nc = 0, Np = 0;
-  std::vector<double> pinv;     // [(nb-1)*(n_e-1)][Np], row (l, k) = l*(n_e-1)+k
+  std::vector<double> pinv;     // [(n_e-1)*(nb-1)][Np], row (k, l) = k*(nb-1)+l
   std::vector<double> binv;     // [(d+1)*d*d][Np], row (s, l, a)
   std::vector<int32_t> gidx;    // [G][Np] gather list: S0 without the cell, then extras
   std::vector<uint8_t> secpos;  // [(d+1)*d][Np] positions in the gather list

@@ -249,7 +249,8 @@ void build_operators(const Geometry& g, const Stencils& st, int M, Operators& op
       }
       if (!pseudo_inverse(NE1, nb - 1, A.data(), P.data()))
         throw Error(CWENO_E_RANK, "rank-deficient least-squares system at cell " + std::to_string(i));
-      for (size_t t = 0; t < P.size(); ++t) op.pinv[t * Np + i] = P[t];
+      for (int l = 0; l < nb - 1; ++l)   // device layout is k-major: row k*(nb-1) + l
+        for (int k = 0; k < NE1; ++k) op.pinv[((size_t)k * (nb - 1) + l) * Np + i] = P[(size_t)l * NE1 + k];
       for (int k = 0; k < G; ++k) op.gidx[(size_t)k * Np + i] = list[k];
       uint8_t mask = 0;
       for (int s = 0; s < ns; ++s) {

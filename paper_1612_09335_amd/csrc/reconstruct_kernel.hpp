@@ -1,8 +1,6 @@
 // CWENO reconstruction kernel for gfx950 (CDNA4).
 //
-// One thread per cell; a thread handles a block of VB variables so that the
-// per-cell operators are streamed from HBM once per block.  Per cell i and
-// variable v (Sec. 2.1):
+// Per cell i and variable v (Sec. 2.1):
 //   (a) P_opt: p_0 = Q_i, p_{1..} = pinv_i (Q_{j(k)} - Q_i)        eq. CWENO:Popt
 //   (b) sector s: p_0 = Q_i, p_{1..d} = binv_{i,s} (Q_{j^s(a)} - Q_i) eq. CWENO:Ps
 //   (c) P_0 = (P_opt - sum_s lambda_s P_s) / lambda_0                eq. CWENO:P0
@@ -14,13 +12,24 @@
 //       (sigma + eps)^r in single precision.
 // Coefficient 0 of the result is a bitwise copy of Q_i (conservation).
 //
+// Work mapping.  A cell is handled by RS adjacent lanes of a wavefront; lane
+// part t owns the P_opt rows l = t, t+RS, ... for all VB variables of the
+// block, so each operator entry is read from HBM exactly once and the
+// per-lane accumulator is ceil((NB-1)/RS) * VB values.  The stencil is
+// walked in chunks of KC entries: the gather indices of the next chunk are
+// loaded while the current chunk's neighbour averages and operator rows are
+// in flight.  Afterwards the rows meet in LDS and lane t finishes the
+// variables v = t, t+RS, ... (steps b-e).
+//
 // Memory layout (structure of arrays, cell index fastest, row stride Np):
-//   pinv[(l * NE1 + k) * Np + i]   l < NB-1, k < NE1
+//   pinv[(k * (NB-1) + l) * Np + i]   k < NE1, l < NB-1
 //   binv[((s * D + l) * D + a) * Np + i]
 //   gidx[k * Np + i] (int32)        k < G: stencil cells then sector extras
 //   secpos[(s * D + a) * Np + i] (uint8), mask[i] (uint8, bit s = sector alive)
 //   q[v * qs + i], out[(v * NB + l) * qs + i] with qs = n_cells
-// so every operator load of a wavefront reads 64 consecutive cells.
+// so the RS lanes of 64/RS consecutive cells read contiguous runs.  Every load
+// is a wave-uniform base (scalar registers) plus a 32-bit per-lane byte
+// offset; the host guarantees that the offsets fit (rows of at most 4 GiB).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -72,46 +81,202 @@ __device__ __forceinline__ T powi(T x, int r) {
   return y;
 }
 
-template <int D, int M, int VB, typename T>
+__host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Load from a wave-uniform base plus a 32-bit per-lane byte offset.
+template <typename T>
+__device__ __forceinline__ T ldo(const T* base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+// LDS bytes a block needs to exchange P_opt rows (0 when RS == 1).
+template <int D, int M, int VB, int RS, typename T>
+__host__ __device__ constexpr int lds_bytes() {
+  return RS == 1 ? 0 : (kThreads / RS) * (nbasis_c(M, D) - 1) * VB * (int)sizeof(T);
+}
+
+// Steps (b)-(e) for one cell and one variable, given P_opt's coefficients
+// 1..NB-1 as popt(l).
+template <int D, int M, typename T, class PoptFn>
+__device__ __forceinline__ void finish_variable(const KParams<T>& p, int64_t i, int v, T qi, PoptFn popt,
+                                                const T (&lam)[D + 2], T inv_l0, const int32_t (&sj)[D + 1][D]) {
+  constexpr int NB = nbasis_c(M, D);
+  constexpr int NL = NB - 1;
+  constexpr int NS = D + 1;
+  const int64_t qs = p.nc, Np = p.Np;
+  const T* __restrict__ q = p.q + (int64_t)(p.v0 + v) * qs;
+  const uint32_t io = (uint32_t)i * (uint32_t)sizeof(T);
+  // (b) sectorial P1 polynomials
+  T ps[NS][D];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    T dqs[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) dqs[a] = ldo(q, (uint32_t)sj[s][a] * (uint32_t)sizeof(T)) - qi;
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+      T x = T(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) x = fma(ldo(p.binv + ((s * D + l) * D + a) * Np, io), dqs[a], x);
+      ps[s][l] = x;
+    }
+  }
+  // (c) P_0
+  T p0[NL];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    T x = popt(l);
+    if (l < D) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) x = fma(-lam[s + 1], ps[s][l], x);
+    }
+    p0[l] = x * inv_l0;
+  }
+  // (d) oscillation indicators (Sigma is symmetric)
+  const T* __restrict__ Sg = p.sigma;
+  T sg[NS + 1];
+  {
+    T x = T(0);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const T pl = p.sigma0_popt ? popt(l) : p0[l];
+      T y = T(0);
+#pragma unroll
+      for (int m = l + 1; m < NL; ++m) y = fma(Sg[l * NL + m], p.sigma0_popt ? popt(m) : p0[m], y);
+      x = fma(pl, fma(T(2), y, Sg[l * NL + l] * pl), x);
+    }
+    sg[0] = x;
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    T x = T(0);
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+      T y = T(0);
+#pragma unroll
+      for (int m = l + 1; m < D; ++m) y = fma(Sg[l * NL + m], ps[s][m], y);
+      x = fma(ps[s][l], fma(T(2), y, Sg[l * NL + l] * ps[s][l]), x);
+    }
+    sg[s + 1] = x;
+  }
+  // (e) nonlinear weights and blend
+  T om[NS + 1];
+  if (p.linear_w) {
+#pragma unroll
+    for (int s = 0; s <= NS; ++s) om[s] = lam[s];
+  } else {
+    T dmin = sg[0] + p.eps;
+#pragma unroll
+    for (int s = 1; s <= NS; ++s)
+      if (lam[s] > T(0)) dmin = fmin(dmin, sg[s] + p.eps);
+    T tot = T(0);
+#pragma unroll
+    for (int s = 0; s <= NS; ++s) {
+      om[s] = lam[s] * powi(dmin / (sg[s] + p.eps), p.r);
+      tot += om[s];
+    }
+    const T inv = T(1) / tot;
+#pragma unroll
+    for (int s = 0; s <= NS; ++s) om[s] *= inv;
+  }
+  T* o = p.out + (int64_t)(p.v0 + v) * NB * qs + i;
+  o[0] = qi;
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    T x = om[0] * p0[l];
+    if (l < D) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) x = fma(om[s + 1], ps[s][l], x);
+    }
+    o[(int64_t)(l + 1) * qs] = x;
+  }
+  if (p.sig) {
+    T* so = p.sig + ((int64_t)(p.v0 + v) * (NS + 1)) * qs + i;
+#pragma unroll
+    for (int s = 0; s <= NS; ++s) so[(int64_t)s * qs] = sg[s];
+  }
+  if (p.om) {
+    T* oo = p.om + ((int64_t)(p.v0 + v) * (NS + 1)) * qs + i;
+#pragma unroll
+    for (int s = 0; s <= NS; ++s) oo[(int64_t)s * qs] = om[s];
+  }
+}
+
+template <int D, int M, int VB, int RS, int KC, typename T>
 __global__ __launch_bounds__(kThreads) void reconstruct_kernel(KParams<T> p) {
   constexpr int NB = nbasis_c(M, D);
   constexpr int NL = NB - 1;
   constexpr int NS = D + 1;
-  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
-  if (i >= p.nc) return;
+  constexpr int NR = ceil_div(NL, RS);       // rows per lane (upper bound)
+  constexpr int CPB = kThreads / RS;         // cells per block
+  const int part = (int)threadIdx.x % RS;
+  const int cl = (int)threadIdx.x / RS;
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * CPB + cl;
+  if constexpr (RS == 1) {
+    if (i >= p.nc) return;
+  }
+  // Lanes past the last cell (RS > 1) work on the last cell and store nothing,
+  // so that every lane reaches the block barrier.
+  const bool valid = i < p.nc;
+  const int64_t ic = valid ? i : p.nc - 1;
   const int64_t Np = p.Np, qs = p.nc;
   const T* __restrict__ q = p.q + (int64_t)p.v0 * qs;
 
+  const uint32_t io = (uint32_t)ic * (uint32_t)sizeof(T);
+  const uint32_t io4 = (uint32_t)ic * 4u;
   T qi[VB];
 #pragma unroll
-  for (int v = 0; v < VB; ++v) qi[v] = q[v * qs + i];
+  for (int v = 0; v < VB; ++v) qi[v] = ldo(q + v * qs, io);
 
-  // (a) P_opt: acc = pinv * dQ, streaming the operator column by column.
-  T acc[NL][VB];
+  T acc[NR][VB];
 #pragma unroll
-  for (int l = 0; l < NL; ++l)
+  for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int v = 0; v < VB; ++v) acc[l][v] = T(0);
+    for (int v = 0; v < VB; ++v) acc[r][v] = T(0);
 
-  const int32_t* __restrict__ gidx = p.gidx + i;
-  const T* __restrict__ pinv = p.pinv + i;
+  // (a) P_opt rows of this lane, stencil walked in chunks of KC
   const int NE1 = p.NE1;
-#pragma unroll 1
-  for (int k = 0; k < NE1; ++k) {
-    const int64_t j = gidx[k * Np];
-    T dq[VB];
+  uint32_t gc[KC];
 #pragma unroll
-    for (int v = 0; v < VB; ++v) dq[v] = q[v * qs + j] - qi[v];
+  for (int kk = 0; kk < KC; ++kk)
+    gc[kk] = kk < NE1 ? (uint32_t)ldo(p.gidx + (int64_t)kk * Np, io4) : (uint32_t)ic;
+  for (int k0 = 0; k0 < NE1; k0 += KC) {
+    uint32_t gn[KC];
 #pragma unroll
-    for (int l = 0; l < NL; ++l) {
-      const T rl = pinv[(int64_t)(l * NE1 + k) * Np];
-#pragma unroll
-      for (int v = 0; v < VB; ++v) acc[l][v] = fma(rl, dq[v], acc[l][v]);
+    for (int kk = 0; kk < KC; ++kk) {
+      const int k = k0 + KC + kk;
+      gn[kk] = k < NE1 ? (uint32_t)ldo(p.gidx + (int64_t)k * Np, io4) : (uint32_t)ic;
     }
+    T dq[KC][VB];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+      for (int v = 0; v < VB; ++v) dq[kk][v] = ldo(q + v * qs, gc[kk] * (uint32_t)sizeof(T)) - qi[v];
+    T rr[KC][NR];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const int k = k0 + kk;
+      const T* __restrict__ row = p.pinv + (int64_t)k * NL * Np;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int l = part + r * RS;
+        rr[kk][r] = (l < NL && k < NE1)
+                        ? ldo(row, (uint32_t)(l * Np + ic) * (uint32_t)sizeof(T))
+                        : T(0);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int v = 0; v < VB; ++v) acc[r][v] = fma(rr[kk][r], dq[kk][v], acc[r][v]);
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) gc[kk] = gn[kk];
   }
 
   // Linear weights of this cell: dropped sectors get 0, the rest renormalised.
-  const unsigned mask = p.mask[i];
+  const unsigned mask = ldo(p.mask, (uint32_t)ic);
   T lam[NS + 1];
   T lsum = p.lam[0];
   lam[0] = p.lam[0];
@@ -123,110 +288,40 @@ __global__ __launch_bounds__(kThreads) void reconstruct_kernel(KParams<T> p) {
 #pragma unroll
   for (int s = 0; s <= NS; ++s) lam[s] /= lsum;
   const T inv_l0 = T(1) / lam[0];
-
-  // Sector cells (indices into the gather list) and their inverse matrices.
   int32_t sj[NS][D];
 #pragma unroll
   for (int s = 0; s < NS; ++s)
 #pragma unroll
-    for (int a = 0; a < D; ++a) sj[s][a] = gidx[(int64_t)p.secpos[(s * D + a) * Np + i] * Np];
+    for (int a = 0; a < D; ++a) {
+      const uint32_t pos = ldo(p.secpos + (s * D + a) * Np, (uint32_t)ic);
+      sj[s][a] = ldo(p.gidx + (int64_t)pos * Np, io4);
+    }
 
-  const T* __restrict__ Sg = p.sigma;
-  T* __restrict__ out = p.out + (int64_t)p.v0 * NB * qs;
-
+  if constexpr (RS == 1) {
 #pragma unroll
-  for (int v = 0; v < VB; ++v) {
-    // (b) sectorial P1 polynomials
-    T ps[NS][D];
+    for (int v = 0; v < VB; ++v)
+      finish_variable<D, M, T>(p, i, v, qi[v], [&](int l) { return acc[l][v]; }, lam, inv_l0, sj);
+  } else {
+    // rows meet in LDS: [cell][l][v]
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* lds = reinterpret_cast<T*>(lds_raw) + (int64_t)cl * NL * VB;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      T dqs[D];
+    for (int r = 0; r < NR; ++r) {
+      const int l = part + r * RS;
+      if (l < NL) {
 #pragma unroll
-      for (int a = 0; a < D; ++a) dqs[a] = q[v * qs + sj[s][a]] - qi[v];
-#pragma unroll
-      for (int l = 0; l < D; ++l) {
-        T x = T(0);
-#pragma unroll
-        for (int a = 0; a < D; ++a) x = fma(p.binv[((s * D + l) * D + a) * Np + i], dqs[a], x);
-        ps[s][l] = x;
+        for (int v = 0; v < VB; ++v) lds[l * VB + v] = acc[r][v];
       }
     }
-    // (c) P_0
-    T p0[NL];
+    __syncthreads();
+    if (!valid) return;
 #pragma unroll
-    for (int l = 0; l < NL; ++l) {
-      T x = acc[l][v];
-      if (l < D) {
-#pragma unroll
-        for (int s = 0; s < NS; ++s) x = fma(-lam[s + 1], ps[s][l], x);
+    for (int m = 0; m < ceil_div(VB, RS); ++m) {
+      const int v = part + m * RS;
+      if (v < VB) {
+        const T qv = ldo(q + (int64_t)v * qs, io);
+        finish_variable<D, M, T>(p, i, v, qv, [&](int l) { return lds[l * VB + v]; }, lam, inv_l0, sj);
       }
-      p0[l] = x * inv_l0;
-    }
-    // (d) oscillation indicators
-    T sg[NS + 1];
-    {
-      T x = T(0);
-#pragma unroll
-      for (int l = 0; l < NL; ++l) {
-        T y = T(0);
-#pragma unroll
-        for (int m = 0; m < NL; ++m) y = fma(Sg[l * NL + m], p.sigma0_popt ? acc[m][v] : p0[m], y);
-        x = fma(p.sigma0_popt ? acc[l][v] : p0[l], y, x);
-      }
-      sg[0] = x;
-    }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      T x = T(0);
-#pragma unroll
-      for (int l = 0; l < D; ++l) {
-        T y = T(0);
-#pragma unroll
-        for (int m = 0; m < D; ++m) y = fma(Sg[l * NL + m], ps[s][m], y);
-        x = fma(ps[s][l], y, x);
-      }
-      sg[s + 1] = x;
-    }
-    // (e) nonlinear weights and blend
-    T om[NS + 1];
-    if (p.linear_w) {
-#pragma unroll
-      for (int s = 0; s <= NS; ++s) om[s] = lam[s];
-    } else {
-      T dmin = sg[0] + p.eps;
-#pragma unroll
-      for (int s = 1; s <= NS; ++s)
-        if (lam[s] > T(0)) dmin = fmin(dmin, sg[s] + p.eps);
-      T tot = T(0);
-#pragma unroll
-      for (int s = 0; s <= NS; ++s) {
-        om[s] = lam[s] * powi(dmin / (sg[s] + p.eps), p.r);
-        tot += om[s];
-      }
-      const T inv = T(1) / tot;
-#pragma unroll
-      for (int s = 0; s <= NS; ++s) om[s] *= inv;
-    }
-    T* o = out + (int64_t)v * NB * qs + i;
-    o[0] = qi[v];
-#pragma unroll
-    for (int l = 0; l < NL; ++l) {
-      T x = om[0] * p0[l];
-      if (l < D) {
-#pragma unroll
-        for (int s = 0; s < NS; ++s) x = fma(om[s + 1], ps[s][l], x);
-      }
-      o[(int64_t)(l + 1) * qs] = x;
-    }
-    if (p.sig) {
-      T* so = p.sig + ((int64_t)(p.v0 + v) * (NS + 1)) * qs + i;
-#pragma unroll
-      for (int s = 0; s <= NS; ++s) so[(int64_t)s * qs] = sg[s];
-    }
-    if (p.om) {
-      T* oo = p.om + ((int64_t)(p.v0 + v) * (NS + 1)) * qs + i;
-#pragma unroll
-      for (int s = 0; s <= NS; ++s) oo[(int64_t)s * qs] = om[s];
     }
   }
 }

@@ -96,3 +96,49 @@ def test_deterministic_and_stream_ordered():
     a = run_library(torch, lm, Q, torch.float64)["coeffs"]
     b = run_library(torch, lm, Q, torch.float64)["coeffs"]
     assert np.array_equal(a.view(np.int64), b.view(np.int64))
+
+
+@pytest.mark.parametrize("case", ["tri13_M3_nv9", "kuhn6_M3_nv5", "tri12_M2_nv4", "tri10_M4_nv5", "kuhn5_M2_nv9"])
+def test_every_variant_bitwise_identical(case):
+    """All kernel variants (lanes per cell, stencil chunk) give the same bits,
+    and the default one matches the oracle."""
+    torch = torch_cuda()
+    C = _lib()
+    if case == "tri13_M3_nv9":
+        m, M, nv = tri_mesh(13, 0.15, 41), 3, 9
+    elif case == "kuhn6_M3_nv5":
+        m, M, nv = kuhn_tet_mesh(6, 0.1, 42), 3, 5
+    elif case == "tri12_M2_nv4":
+        m, M, nv = tri_mesh(12, 0.15, 43), 2, 4
+    elif case == "tri10_M4_nv5":
+        m, M, nv = tri_mesh(10, 0.15, 44), 4, 5
+    else:
+        m, M, nv = kuhn_tet_mesh(5, 0.1, 45), 2, 9
+    rng = np.random.default_rng(46)
+    Q = rng.normal(size=(nv, m.n_cells)) + 3.0 * (rng.random((1, m.n_cells)) < 0.3)
+    print(f"[gpu variants] {case}", flush=True)
+    for dt, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        lm = C.Mesh(m.vertices, m.cells, M, periodic=m.box, ops=dt)
+        base = run_library(torch, lm, Q, tdt)
+        seen = 0
+        for vb in range(1, 10):
+            k0 = lm.get_variant(dt, vb)[0]
+            if k0 < 0:
+                continue
+            for k in range(C.num_variants()):
+                try:
+                    lm.set_variant(dt, vb, k)
+                except C.CwenoError:
+                    continue
+                res = run_library(torch, lm, Q, tdt)
+                for key in ("coeffs", "sigma", "omega"):
+                    assert np.array_equal(res[key], base[key]), (dt, vb, k, key)
+                seen += 1
+            lm.set_variant(dt, vb, k0)
+        assert seen >= 6
+        if dt == "f64":
+            o = CwenoOracle(m.vertices, m.cells, m.box, Options(degree=M))
+            ref = o.reconstruct(Q, cells=range(0, m.n_cells, 7))
+            idx = np.arange(0, m.n_cells, 7)
+            err = data_scaled_error(base["coeffs"][:, :, idx], ref["coeffs"], Q, lm.tables()["stencil"][idx])
+            assert err <= TOL64
