@@ -65,6 +65,7 @@ def load_traffic(tag):
 
 def time_path(torch, mesh, q, steps, warmup):
     out = torch.empty((q.shape[0], mesh.n_basis, mesh.n_cells), dtype=q.dtype, device=q.device)
+    mesh.tune(q, out, repeats=5)            # the library's autotuner picks the kernel variant
     for _ in range(warmup):
         mesh.reconstruct(q, out=out)
     torch.cuda.synchronize()
@@ -109,7 +110,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(1 << 28, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": a.numel() * 8, "launches": 3}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the reconstruction of a mesh runs on a single device "
               "(multi-GPU sharding is a design note, not implemented); run with --gpus 1", file=sys.stderr)
@@ -154,7 +166,8 @@ def main():
             roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                           frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                           algorithmic_bytes_per_cell=bpc, algorithmic_bytes_per_launch=bytes_launch))
-        log(f"{tag}: {ms:.4f} ms/step, {res[tag]['value']:.3e} cells*vars/s, {achieved:.0f} GB/s "
+        res[tag]["variant"] = lm.get_variant(tag, nv)
+        log(f"{tag}: variant {res[tag]['variant']}, {ms:.4f} ms/step, {res[tag]['value']:.3e} cells*vars/s, {achieved:.0f} GB/s "
             f"({100 * achieved / HBM_PEAK_GBS:.1f}% of peak)")
 
     cpu = None
@@ -175,6 +188,7 @@ def main():
                    "lambda0": 0.95, "eps": 1e-14, "r": 4, "seed": SEED},
         "roofline": r64["roofline"],
         "latency_ms": r64["latency_ms"],
+        "kernel_variant": {"f64": res["f64"]["variant"], "f32": res["f32"]["variant"]},
         "fp32": {"value": res["f32"]["value"], "ms_per_step": res["f32"]["ms_per_step"],
                  "latency_ms": res["f32"]["latency_ms"], "roofline": res["f32"]["roofline"],
                  "dtype": "f32"},

@@ -131,7 +131,7 @@ class Mesh:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:
             lib.cweno_mesh_destroy(h)
             self._h = None
 

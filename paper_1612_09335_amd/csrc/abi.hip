@@ -81,7 +81,7 @@ cweno_status upload_f32(DevBuf& b, const std::vector<double>& src, hipStream_t s
 
 // Default variant: the candidate order below, first one instantiated for the block.
 int default_variant(int d, int M, int vb, bool f32) {
-  const int order[] = {4, 2, 5, 3, 1, 0};   // (4,2) (2,2) (4,4) (2,4) (1,2) (1,1)
+  const int order[] = {1, 0, 2, 3, 4, 5};   // (1,2) (1,1) (2,2) (2,4) (4,2) (4,4)
   for (int k : order)
     if (cweno::vb_allowed(d, M, vb, cweno::kVariants[k].rs, f32)) return k;
   return -1;
