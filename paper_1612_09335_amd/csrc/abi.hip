@@ -43,13 +43,15 @@ struct cweno_mesh {
   cweno::Operators op;  // FP64 operators (host copy kept only for host-only meshes)
   // device residency
   int device = -1;
-  DevBuf pinv64, binv64, sigma64, pinv32, binv32, sigma32, gidx, secpos, mask;
+  DevBuf pinv64, binv64, sigma64, pinv32, binv32, sigma32, gidx, secpos, mask, halo, hoff, lidx;
+  int maxH = 0;
   int64_t device_bytes = 0;
   // kernel variant (index into cweno::kVariants) per [precision][variable block]
   int variant[2][10];
 
   ~cweno_mesh() {
-    for (DevBuf* b : {&pinv64, &binv64, &sigma64, &pinv32, &binv32, &sigma32, &gidx, &secpos, &mask})
+    for (DevBuf* b : {&pinv64, &binv64, &sigma64, &pinv32, &binv32, &sigma32, &gidx, &secpos, &mask, &halo,
+                      &hoff, &lidx})
       if (b->p) (void)hipFree(b->p);
   }
 };
@@ -79,11 +81,20 @@ cweno_status upload_f32(DevBuf& b, const std::vector<double>& src, hipStream_t s
   return upload(b, tmp.data(), tmp.size() * sizeof(float), s, total);
 }
 
-// Default variant: the candidate order below, first one instantiated for the block.
-int default_variant(int d, int M, int vb, bool f32) {
-  const int order[] = {1, 0, 2, 3, 4, 5};   // (1,2) (1,1) (2,2) (2,4) (4,2) (4,4)
+// Whether variant k can run blocks of vb variables on this mesh: instantiated,
+// and for the halo kernel, the block halos fit in LDS.
+bool variant_ok(const cweno_mesh* m, int vb, int k, bool f32) {
+  const cweno::Variant& V = cweno::kVariants[k];
+  if (!cweno::variant_allowed(m->d, m->M, vb, V, f32)) return false;
+  if (V.pc == 2) return m->maxH > 0 && (int64_t)m->maxH * vb * (f32 ? 4 : 8) <= cweno::kMaxLds;
+  return true;
+}
+
+// Default variant: the candidate order below, first one that can run.
+int default_variant(const cweno_mesh* m, int vb, bool f32) {
+  const int order[] = {10, 9, 11, 1, 0, 2, 3, 4, 5, 6, 7, 8};
   for (int k : order)
-    if (cweno::vb_allowed(d, M, vb, cweno::kVariants[k].rs, f32)) return k;
+    if (variant_ok(m, vb, k, f32)) return k;
   return -1;
 }
 
@@ -101,6 +112,11 @@ cweno::KParams<T> make_params(const cweno_mesh* m, const void* q, void* coeffs, 
   p.gidx = (const int32_t*)m->gidx.p;
   p.secpos = (const uint8_t*)m->secpos.p;
   p.mask = (const uint8_t*)m->mask.p;
+  p.halo = (const int32_t*)m->halo.p;
+  p.hoff = (const int32_t*)m->hoff.p;
+  p.lidx = (const uint16_t*)m->lidx.p;
+  p.maxH = m->maxH;
+  p.G = m->G;
   p.nc = m->nc;
   p.Np = m->Np;
   p.NE1 = m->n_e - 1;
@@ -116,10 +132,9 @@ cweno::KParams<T> make_params(const cweno_mesh* m, const void* q, void* coeffs, 
 // Launch one variable block [v0, v0+vb) with variant index k.
 hipError_t launch_block(const cweno_mesh* m, bool f32, const void* q, void* coeffs, void* sigma, void* omega,
                         int v0, int vb, int k, hipStream_t s) {
-  const cweno::Variant& V = cweno::kVariants[k];
   if (f32)
-    return cweno::launch<float>(m->d, m->M, make_params<float>(m, q, coeffs, sigma, omega, v0), vb, V.rs, V.kc, s);
-  return cweno::launch<double>(m->d, m->M, make_params<double>(m, q, coeffs, sigma, omega, v0), vb, V.rs, V.kc, s);
+    return cweno::launch<float>(m->d, m->M, make_params<float>(m, q, coeffs, sigma, omega, v0), vb, k, s);
+  return cweno::launch<double>(m->d, m->M, make_params<double>(m, q, coeffs, sigma, omega, v0), vb, k, s);
 }
 
 cweno_status check_reconstruct_args(const cweno_mesh* m, int n_vars, cweno_dtype dtype, const void* q,
@@ -239,8 +254,6 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
   if ((uint64_t)(m->nb - 1) * (uint64_t)m->Np * 8u >= (uint64_t(1) << 32))
     return fail(CWENO_E_ARG, "mesh too large for one device operator block (split it)");
   m->n_dropped = m->op.n_dropped;
-  for (int t = 0; t < 2; ++t)
-    for (int vb = 0; vb < 10; ++vb) m->variant[t][vb] = vb == 0 ? -1 : default_variant(dim, degree, vb, t == 1);
 
   if (!(o.flags & CWENO_FLAG_HOST_ONLY)) {
     hipStream_t s = (hipStream_t)hip_stream;
@@ -260,12 +273,24 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
     if ((st = upload(m->gidx, op.gidx.data(), op.gidx.size() * 4, s, m->device_bytes))) return st;
     if ((st = upload(m->secpos, op.secpos.data(), op.secpos.size(), s, m->device_bytes))) return st;
     if ((st = upload(m->mask, op.mask.data(), op.mask.size(), s, m->device_bytes))) return st;
+    try {
+      cweno::Halo h;
+      cweno::build_halo(op, cweno::kHaloBlock, h);
+      if ((st = upload(m->halo, h.cells.data(), h.cells.size() * 4, s, m->device_bytes))) return st;
+      if ((st = upload(m->hoff, h.offset.data(), h.offset.size() * 4, s, m->device_bytes))) return st;
+      if ((st = upload(m->lidx, h.lidx.data(), h.lidx.size() * 2, s, m->device_bytes))) return st;
+      m->maxH = h.max_len;
+    } catch (const cweno::Error&) {
+      m->maxH = 0;   // halos too large: the halo kernel is not used for this mesh
+    }
     // the device holds the operators now; keep only what the host-side dumps need
     std::vector<double>().swap(m->op.pinv);
     std::vector<double>().swap(m->op.binv);
     std::vector<int32_t>().swap(m->op.gidx);
     std::vector<uint8_t>().swap(m->op.secpos);
   }
+  for (int t = 0; t < 2; ++t)
+    for (int vb = 0; vb < 10; ++vb) m->variant[t][vb] = vb == 0 ? -1 : default_variant(m.get(), vb, t == 1);
   *out = m.release();
   return CWENO_OK;
 }
@@ -333,7 +358,7 @@ cweno_status cweno_mesh_set_variant(cweno_mesh* m, cweno_dtype dtype, int vb, in
   if (dtype != CWENO_F64 && dtype != CWENO_F32) return fail(CWENO_E_ARG, "bad dtype");
   if (vb < 1 || vb > 9) return fail(CWENO_E_ARG, "variable block out of range");
   if (variant < 0 || variant >= cweno::kNumVariants) return fail(CWENO_E_ARG, "variant out of range");
-  if (!cweno::vb_allowed(m->d, m->M, vb, cweno::kVariants[variant].rs, dtype == CWENO_F32))
+  if (!variant_ok(m, vb, variant, dtype == CWENO_F32))
     return fail(CWENO_E_ARG, "variant not instantiated for this block");
   m->variant[dtype == CWENO_F32][vb] = variant;
   return CWENO_OK;
@@ -373,7 +398,7 @@ cweno_status cweno_mesh_tune(cweno_mesh* m, int n_vars, cweno_dtype dtype, const
     float best = 0.0f;
     int best_k = -1;
     for (int k = 0; k < cweno::kNumVariants && st == CWENO_OK; ++k) {
-      if (!cweno::vb_allowed(m->d, m->M, vb, cweno::kVariants[k].rs, f32)) continue;
+      if (!variant_ok(m, vb, k, f32)) continue;
       hipError_t e = launch_block(m, f32, q, coeffs, nullptr, nullptr, v0, vb, k, s);   // warm-up
       if (e == hipSuccess) e = hipEventRecord(e0, s);
       for (int t = 0; t < repeats && e == hipSuccess; ++t)

@@ -86,6 +86,18 @@ struct Operators {
   int64_t n_dropped = 0;
 };
 
+// Per-block halos: for each block of B consecutive cells, the sorted unique
+// cells its gather lists reference (its own cells included), and every gather
+// index re-expressed as a 16-bit position in that list.
+struct Halo {
+  int B = 0;
+  int max_len = 0;                 // largest halo of any block
+  std::vector<int32_t> cells;      // concatenated halos
+  std::vector<int32_t> offset;     // [n_blocks + 1]
+  std::vector<uint16_t> lidx;      // [G+1][Np] position of gidx[k][i] in i's block halo; row G: cell i itself
+};
+void build_halo(const Operators& op, int B, Halo& h);
+
 double min_image(double delta, double L);
 void build_geometry(const MeshInput& in, Geometry& g);
 void face_adjacency(const MeshInput& in, std::vector<int32_t>& nbr);

@@ -55,6 +55,11 @@ struct KParams {
   const int32_t* gidx;
   const uint8_t* secpos;
   const uint8_t* mask;
+  const int32_t* halo;     // concatenated per-block halos (halo kernel)
+  const int32_t* hoff;     // [n_blocks + 1]
+  const uint16_t* lidx;    // [G+1][Np] gather entries as positions in the block halo; row G: the cell
+  int maxH;                // largest halo
+  int G;                   // gather-list length
   int64_t nc;      // cells
   int64_t Np;      // operator row stride
   int NE1;         // stencil cells besides i
@@ -95,29 +100,36 @@ __host__ __device__ constexpr int lds_bytes() {
   return RS == 1 ? 0 : (kThreads / RS) * (nbasis_c(M, D) - 1) * VB * (int)sizeof(T);
 }
 
+// Sector differences Q_j - Q_i of variable v gathered from global memory.
+template <int D, typename T>
+__device__ __forceinline__ void sector_dq_global(const KParams<T>& p, int v, T qi, const int32_t (&sj)[D + 1][D],
+                                                 T (&dqs)[D + 1][D]) {
+  const T* __restrict__ q = p.q + (int64_t)(p.v0 + v) * p.nc;
+#pragma unroll
+  for (int s = 0; s <= D; ++s)
+#pragma unroll
+    for (int a = 0; a < D; ++a) dqs[s][a] = ldo(q, (uint32_t)sj[s][a] * (uint32_t)sizeof(T)) - qi;
+}
+
 // Steps (b)-(e) for one cell and one variable, given P_opt's coefficients
-// 1..NB-1 as popt(l).
+// 1..NB-1 as popt(l) and the sector differences dqs[s][a] = Q_{j^s(a)} - Q_i.
 template <int D, int M, typename T, class PoptFn>
 __device__ __forceinline__ void finish_variable(const KParams<T>& p, int64_t i, int v, T qi, PoptFn popt,
-                                                const T (&lam)[D + 2], T inv_l0, const int32_t (&sj)[D + 1][D]) {
+                                                const T (&lam)[D + 2], T inv_l0, const T (&dqs)[D + 1][D]) {
   constexpr int NB = nbasis_c(M, D);
   constexpr int NL = NB - 1;
   constexpr int NS = D + 1;
   const int64_t qs = p.nc, Np = p.Np;
-  const T* __restrict__ q = p.q + (int64_t)(p.v0 + v) * qs;
   const uint32_t io = (uint32_t)i * (uint32_t)sizeof(T);
   // (b) sectorial P1 polynomials
   T ps[NS][D];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    T dqs[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) dqs[a] = ldo(q, (uint32_t)sj[s][a] * (uint32_t)sizeof(T)) - qi;
 #pragma unroll
     for (int l = 0; l < D; ++l) {
       T x = T(0);
 #pragma unroll
-      for (int a = 0; a < D; ++a) x = fma(ldo(p.binv + ((s * D + l) * D + a) * Np, io), dqs[a], x);
+      for (int a = 0; a < D; ++a) x = fma(ldo(p.binv + ((s * D + l) * D + a) * Np, io), dqs[s][a], x);
       ps[s][l] = x;
     }
   }
@@ -299,8 +311,11 @@ __global__ __launch_bounds__(kThreads) void reconstruct_kernel(KParams<T> p) {
 
   if constexpr (RS == 1) {
 #pragma unroll
-    for (int v = 0; v < VB; ++v)
-      finish_variable<D, M, T>(p, i, v, qi[v], [&](int l) { return acc[l][v]; }, lam, inv_l0, sj);
+    for (int v = 0; v < VB; ++v) {
+      T dqs[NS][D];
+      sector_dq_global<D, T>(p, v, qi[v], sj, dqs);
+      finish_variable<D, M, T>(p, i, v, qi[v], [&](int l) { return acc[l][v]; }, lam, inv_l0, dqs);
+    }
   } else {
     // rows meet in LDS: [cell][l][v]
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -320,7 +335,9 @@ __global__ __launch_bounds__(kThreads) void reconstruct_kernel(KParams<T> p) {
       const int v = part + m * RS;
       if (v < VB) {
         const T qv = ldo(q + (int64_t)v * qs, io);
-        finish_variable<D, M, T>(p, i, v, qv, [&](int l) { return lds[l * VB + v]; }, lam, inv_l0, sj);
+        T dqs[NS][D];
+        sector_dq_global<D, T>(p, v, qv, sj, dqs);
+        finish_variable<D, M, T>(p, i, v, qv, [&](int l) { return lds[l * VB + v]; }, lam, inv_l0, dqs);
       }
     }
   }
