@@ -189,8 +189,9 @@ cweno_status cweno_mesh_operators(const cweno_mesh* mesh, int64_t cell, double* 
  *
  * Asynchronous: it enqueues kernels and returns; it neither allocates nor
  * synchronises.  Buffers are owned by the caller and must stay valid until
- * the stream has executed the work.  Errors: CWENO_E_ARG (bad sizes, host-only
- * mesh, missing operator precision), CWENO_E_HIP (launch failure).
+ * the stream has executed the work.  The four buffers must not overlap.
+ * Errors: CWENO_E_ARG (bad sizes, host-only mesh, missing operator precision,
+ * overlapping buffers), CWENO_E_HIP (launch failure).
  */
 cweno_status cweno_reconstruct(const cweno_mesh* mesh, int n_vars, cweno_dtype dtype,
                                const void* q, void* coeffs, void* sigma, void* omega,
@@ -199,18 +200,22 @@ cweno_status cweno_reconstruct(const cweno_mesh* mesh, int n_vars, cweno_dtype d
 /*
  * Kernel variants and their autotuner.
  *
- * The reconstruction kernel exists in several variants (cweno_num_variants()):
- * variant k assigns RS lanes of a wavefront to each cell, each lane owning
- * every RS-th row of the P_opt operator, and walks the stencil in chunks of
- * KC entries.  All variants compute the same values (the per-lane sums run
- * over the stencil in the same order); they differ only in speed.  A mesh
- * keeps one variant per (precision, variable block); variables are processed
- * in blocks of at most 9 (the block sizes instantiated for the mesh's degree
- * and dimension), each block reading the operators once.
+ * The reconstruction kernel exists in several variants (cweno_num_variants()).
+ * Kind 0 gathers the neighbour averages of each cell's stencil from global
+ * memory; kind 1 first copies, per workgroup of 256 consecutive cells, the
+ * averages of every cell their stencils reference (the block's halo, listed
+ * by the library at cweno_mesh_create) into LDS and reads the stencils from
+ * there.  Both walk the stencil in chunks of KC entries.  All variants
+ * compute the same values (the per-lane sums run over the stencil in the same
+ * order); they differ only in speed.  Kind 1 is available only when every
+ * block's halo fits in LDS.  A mesh keeps one variant per (precision,
+ * variable block); variables are processed in blocks of at most 9 (the block
+ * sizes instantiated for the mesh's degree and dimension), each block reading
+ * the operators once.
  *
  * cweno_mesh_set_variant  choose variant `variant` for blocks of `vb` variables
  *                         (CWENO_E_ARG if that combination is not instantiated)
- * cweno_mesh_get_variant  report the current choice (variant index, RS, KC)
+ * cweno_mesh_get_variant  report the current choice (variant index, kind, KC)
  * cweno_mesh_tune         time every instantiated variant for each block that a
  *                         cweno_reconstruct of n_vars variables would launch,
  *                         using the caller's device buffers q [n_vars][n_cells]
@@ -222,7 +227,7 @@ cweno_status cweno_reconstruct(const cweno_mesh* mesh, int n_vars, cweno_dtype d
  */
 int cweno_num_variants(void);
 cweno_status cweno_mesh_set_variant(cweno_mesh* mesh, cweno_dtype dtype, int vb, int variant);
-cweno_status cweno_mesh_get_variant(const cweno_mesh* mesh, cweno_dtype dtype, int vb, int* variant, int* rs,
+cweno_status cweno_mesh_get_variant(const cweno_mesh* mesh, cweno_dtype dtype, int vb, int* variant, int* kind,
                                     int* kc);
 cweno_status cweno_mesh_tune(cweno_mesh* mesh, int n_vars, cweno_dtype dtype, const void* q, void* coeffs,
                              int repeats, void* hip_stream, double* best_ms);

@@ -192,10 +192,11 @@ class Mesh:
         _check(lib.cweno_mesh_set_variant(self._h, {"f64": F64, "f32": F32}[dtype], vb, variant))
 
     def get_variant(self, dtype: str, vb: int):
-        k, rs, kc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        """(variant index, kind: 0 direct gathers / 1 LDS halo, stencil chunk KC)."""
+        k, kind, kc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(lib.cweno_mesh_get_variant(self._h, {"f64": F64, "f32": F32}[dtype], vb, ctypes.byref(k),
-                                          ctypes.byref(rs), ctypes.byref(kc)))
-        return k.value, rs.value, kc.value
+                                          ctypes.byref(kind), ctypes.byref(kc)))
+        return k.value, kind.value, kc.value
 
     def tune(self, q, out=None, repeats: int = 5, stream=None) -> float:
         """cweno_mesh_tune on the given averages; returns the tuned time (ms)."""

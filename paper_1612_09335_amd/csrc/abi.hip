@@ -86,13 +86,13 @@ cweno_status upload_f32(DevBuf& b, const std::vector<double>& src, hipStream_t s
 bool variant_ok(const cweno_mesh* m, int vb, int k, bool f32) {
   const cweno::Variant& V = cweno::kVariants[k];
   if (!cweno::variant_allowed(m->d, m->M, vb, V, f32)) return false;
-  if (V.pc == 2) return m->maxH > 0 && (int64_t)m->maxH * vb * (f32 ? 4 : 8) <= cweno::kMaxLds;
+  if (V.kind == 1) return m->maxH > 0 && (int64_t)m->maxH * vb * (f32 ? 4 : 8) <= cweno::kMaxLds;
   return true;
 }
 
 // Default variant: the candidate order below, first one that can run.
 int default_variant(const cweno_mesh* m, int vb, bool f32) {
-  const int order[] = {10, 9, 11, 1, 0, 2, 3, 4, 5, 6, 7, 8};
+  const int order[] = {3, 2, 4, 1, 0};
   for (int k : order)
     if (variant_ok(m, vb, k, f32)) return k;
   return -1;
@@ -137,8 +137,15 @@ hipError_t launch_block(const cweno_mesh* m, bool f32, const void* q, void* coef
   return cweno::launch<double>(m->d, m->M, make_params<double>(m, q, coeffs, sigma, omega, v0), vb, k, s);
 }
 
+// Whether [a, a + na) and [b, b + nb) share a byte (empty ranges never do).
+bool overlap(const void* a, uint64_t na, const void* b, uint64_t nb) {
+  if (!a || !b || !na || !nb) return false;
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
 cweno_status check_reconstruct_args(const cweno_mesh* m, int n_vars, cweno_dtype dtype, const void* q,
-                                    const void* coeffs) {
+                                    const void* coeffs, const void* sigma, const void* omega) {
   if (!m) return fail(CWENO_E_ARG, "mesh is NULL");
   if (n_vars < 1) return fail(CWENO_E_ARG, "n_vars must be >= 1");
   if (!q || !coeffs) return fail(CWENO_E_ARG, "q and coeffs must be device pointers");
@@ -150,6 +157,12 @@ cweno_status check_reconstruct_args(const cweno_mesh* m, int n_vars, cweno_dtype
   // neighbour averages are gathered with 32-bit byte offsets within one variable
   if ((uint64_t)m->nc * (f32 ? 4u : 8u) >= (uint64_t(1) << 32))
     return fail(CWENO_E_ARG, "too many cells for 32-bit offsets");
+  // the kernels take every buffer as non-aliasing
+  const uint64_t es = f32 ? 4 : 8, cells = (uint64_t)m->nc * (uint64_t)n_vars;
+  const uint64_t nq = cells * es, nco = cells * (uint64_t)m->nb * es, nd = cells * (uint64_t)(m->d + 2) * es;
+  if (overlap(q, nq, coeffs, nco) || overlap(q, nq, sigma, nd) || overlap(q, nq, omega, nd) ||
+      overlap(coeffs, nco, sigma, nd) || overlap(coeffs, nco, omega, nd) || overlap(sigma, nd, omega, nd))
+    return fail(CWENO_E_ARG, "q, coeffs, sigma and omega must not overlap");
   return CWENO_OK;
 }
 
@@ -339,7 +352,7 @@ cweno_status cweno_mesh_operators(const cweno_mesh* m, int64_t cell, double* pin
 
 cweno_status cweno_reconstruct(const cweno_mesh* m, int n_vars, cweno_dtype dtype, const void* q, void* coeffs,
                                void* sigma, void* omega, void* hip_stream) {
-  cweno_status st = check_reconstruct_args(m, n_vars, dtype, q, coeffs);
+  cweno_status st = check_reconstruct_args(m, n_vars, dtype, q, coeffs, sigma, omega);
   if (st) return st;
   hipStream_t s = (hipStream_t)hip_stream;
   const bool f32 = dtype == CWENO_F32;
@@ -364,14 +377,14 @@ cweno_status cweno_mesh_set_variant(cweno_mesh* m, cweno_dtype dtype, int vb, in
   return CWENO_OK;
 }
 
-cweno_status cweno_mesh_get_variant(const cweno_mesh* m, cweno_dtype dtype, int vb, int* variant, int* rs,
+cweno_status cweno_mesh_get_variant(const cweno_mesh* m, cweno_dtype dtype, int vb, int* variant, int* kind,
                                     int* kc) {
   if (!m) return fail(CWENO_E_ARG, "mesh is NULL");
   if (dtype != CWENO_F64 && dtype != CWENO_F32) return fail(CWENO_E_ARG, "bad dtype");
   if (vb < 1 || vb > 9) return fail(CWENO_E_ARG, "variable block out of range");
   const int k = m->variant[dtype == CWENO_F32][vb];
   if (variant) *variant = k;
-  if (rs) *rs = k >= 0 ? cweno::kVariants[k].rs : 0;
+  if (kind) *kind = k >= 0 ? cweno::kVariants[k].kind : -1;
   if (kc) *kc = k >= 0 ? cweno::kVariants[k].kc : 0;
   return CWENO_OK;
 }
@@ -380,7 +393,7 @@ int cweno_num_variants(void) { return cweno::kNumVariants; }
 
 cweno_status cweno_mesh_tune(cweno_mesh* m, int n_vars, cweno_dtype dtype, const void* q, void* coeffs,
                              int repeats, void* hip_stream, double* best_ms) {
-  cweno_status st = check_reconstruct_args(m, n_vars, dtype, q, coeffs);
+  cweno_status st = check_reconstruct_args(m, n_vars, dtype, q, coeffs, nullptr, nullptr);
   if (st) return st;
   if (repeats < 1) return fail(CWENO_E_ARG, "repeats must be >= 1");
   hipStream_t s = (hipStream_t)hip_stream;

@@ -23,7 +23,8 @@ namespace cweno {
 constexpr int kHaloBlock = 256;   // cells (and threads) per workgroup; fixed by the host's halo lists
 
 template <int D, int M, int VB, int KC, typename T>
-__global__ __launch_bounds__(kHaloBlock) void reconstruct_halo_kernel(KParams<T> p) {
+__global__ __launch_bounds__(kHaloBlock) void reconstruct_halo_kernel(KParams<T> p, CWENO_ARRAY_PARAMS(T)) {
+  CWENO_BIND_ARRAYS(p);
   constexpr int NB = nbasis_c(M, D);
   constexpr int NL = NB - 1;
   constexpr int NS = D + 1;

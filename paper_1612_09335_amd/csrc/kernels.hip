@@ -24,26 +24,12 @@ typedef float real_t;
 namespace cweno {
 namespace {
 
-template <int VB, int RS, int KC>
-hipError_t launch_one(const KParams<real_t>& p, hipStream_t s) {
-  if constexpr (vb_allowed(CWENO_D, CWENO_M, VB, RS, sizeof(real_t) == 4)) {
-    constexpr int cpb = kThreads / RS;
-    const int64_t blocks = (p.nc + cpb - 1) / cpb;
-    constexpr int lds = lds_bytes<CWENO_D, CWENO_M, VB, RS, real_t>();
-    hipLaunchKernelGGL((reconstruct_kernel<CWENO_D, CWENO_M, VB, RS, KC, real_t>), dim3((unsigned)blocks),
-                       dim3(kThreads), lds, s, p);
-    return hipGetLastError();
-  } else {
-    return hipErrorInvalidValue;
-  }
-}
-
-template <int VB, int NCW, int DP, int P>
-hipError_t launch_pc(const KParams<real_t>& p, hipStream_t s) {
-  if constexpr (pc_allowed(CWENO_D, CWENO_M, VB, NCW, DP, sizeof(real_t) == 4)) {
-    const int64_t blocks = (p.nc + 64 * NCW - 1) / (64 * NCW);
-    hipLaunchKernelGGL((reconstruct_pc_kernel<CWENO_D, CWENO_M, VB, NCW, DP, P, real_t>), dim3((unsigned)blocks),
-                       dim3(64 * (NCW + 1)), 0, s, p);
+template <int VB, int KC>
+hipError_t launch_direct(const KParams<real_t>& p, hipStream_t s) {
+  if constexpr (vb_allowed(CWENO_D, CWENO_M, VB, sizeof(real_t) == 4)) {
+    const int64_t blocks = (p.nc + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL((reconstruct_kernel<CWENO_D, CWENO_M, VB, KC, real_t>), dim3((unsigned)blocks),
+                       dim3(kThreads), 0, s, p, CWENO_ARRAY_ARGS(p));
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -52,16 +38,16 @@ hipError_t launch_pc(const KParams<real_t>& p, hipStream_t s) {
 
 template <int VB, int KC>
 hipError_t launch_halo(const KParams<real_t>& p, hipStream_t s) {
-  if constexpr (vb_allowed(CWENO_D, CWENO_M, VB, 1, sizeof(real_t) == 4)) {
+  if constexpr (vb_allowed(CWENO_D, CWENO_M, VB, sizeof(real_t) == 4)) {
     const int64_t blocks = (p.nc + kHaloBlock - 1) / kHaloBlock;
     const size_t lds = (size_t)p.maxH * VB * sizeof(real_t);
-    if (lds > (size_t)kMaxLds) return hipErrorInvalidValue;
+    if (p.maxH <= 0 || lds > (size_t)kMaxLds) return hipErrorInvalidValue;
     auto fn = reconstruct_halo_kernel<CWENO_D, CWENO_M, VB, KC, real_t>;
     if (lds > 65536) {
       hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kHaloBlock), lds, s, p);
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kHaloBlock), lds, s, p, CWENO_ARRAY_ARGS(p));
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -71,18 +57,11 @@ hipError_t launch_halo(const KParams<real_t>& p, hipStream_t s) {
 template <int VB>
 hipError_t launch_variant(const KParams<real_t>& p, int k, hipStream_t s) {
   switch (k) {
-    case 0: return launch_one<VB, 1, 1>(p, s);
-    case 1: return launch_one<VB, 1, 2>(p, s);
-    case 2: return launch_one<VB, 2, 2>(p, s);
-    case 3: return launch_one<VB, 2, 4>(p, s);
-    case 4: return launch_one<VB, 4, 2>(p, s);
-    case 5: return launch_one<VB, 4, 4>(p, s);
-    case 6: return launch_pc<VB, 3, 3, 1>(p, s);
-    case 7: return launch_pc<VB, 2, 4, 1>(p, s);
-    case 8: return launch_pc<VB, 1, 5, 1>(p, s);
-    case 9: return launch_halo<VB, 1>(p, s);
-    case 10: return launch_halo<VB, 2>(p, s);
-    case 11: return launch_halo<VB, 4>(p, s);
+    case 0: return launch_direct<VB, 1>(p, s);
+    case 1: return launch_direct<VB, 2>(p, s);
+    case 2: return launch_halo<VB, 1>(p, s);
+    case 3: return launch_halo<VB, 2>(p, s);
+    case 4: return launch_halo<VB, 4>(p, s);
     default: return hipErrorInvalidValue;
   }
 }

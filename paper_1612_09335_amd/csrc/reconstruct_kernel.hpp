@@ -12,14 +12,11 @@
 //       (sigma + eps)^r in single precision.
 // Coefficient 0 of the result is a bitwise copy of Q_i (conservation).
 //
-// Work mapping.  A cell is handled by RS adjacent lanes of a wavefront; lane
-// part t owns the P_opt rows l = t, t+RS, ... for all VB variables of the
-// block, so each operator entry is read from HBM exactly once and the
-// per-lane accumulator is ceil((NB-1)/RS) * VB values.  The stencil is
-// walked in chunks of KC entries: the gather indices of the next chunk are
-// loaded while the current chunk's neighbour averages and operator rows are
-// in flight.  Afterwards the rows meet in LDS and lane t finishes the
-// variables v = t, t+RS, ... (steps b-e).
+// Work mapping.  One lane per cell; the lane keeps (NB-1) * VB accumulators
+// for the VB variables of the block, so each operator entry is read from HBM
+// exactly once.  The stencil is walked in chunks of KC entries: the gather
+// indices of the next chunk are loaded while the current chunk's neighbour
+// averages and operator rows are in flight.
 //
 // Memory layout (structure of arrays, cell index fastest, row stride Np):
 //   pinv[(k * (NB-1) + l) * Np + i]   k < NE1, l < NB-1
@@ -27,7 +24,7 @@
 //   gidx[k * Np + i] (int32)        k < G: stencil cells then sector extras
 //   secpos[(s * D + a) * Np + i] (uint8), mask[i] (uint8, bit s = sector alive)
 //   q[v * qs + i], out[(v * NB + l) * qs + i] with qs = n_cells
-// so the RS lanes of 64/RS consecutive cells read contiguous runs.  Every load
+// so the lanes of a wavefront read contiguous runs.  Every load
 // is a wave-uniform base (scalar registers) plus a 32-bit per-lane byte
 // offset; the host guarantees that the offsets fit (rows of at most 4 GiB).
 #pragma once
@@ -71,6 +68,27 @@ struct KParams {
   T eps;
 };
 
+// Every array also reaches a kernel as an argument of its own, marked
+// __restrict__: the arrays never overlap (the library rejects overlapping
+// caller buffers), and saying so lets the compiler keep the sector operators
+// in registers and read the universal Sigma through the scalar cache instead
+// of reloading both after every store of a coefficient.  A kernel rebinds the
+// fields of its KParams to these arguments on entry.
+#define CWENO_ARRAY_PARAMS(T)                                                                          \
+  const T* __restrict__ a_q, T* __restrict__ a_out, T* __restrict__ a_sig, T* __restrict__ a_om,       \
+      const T* __restrict__ a_pinv, const T* __restrict__ a_binv, const T* __restrict__ a_sigma,       \
+      const int32_t* __restrict__ a_gidx, const uint8_t* __restrict__ a_secpos,                         \
+      const uint8_t* __restrict__ a_mask, const int32_t* __restrict__ a_halo,                           \
+      const int32_t* __restrict__ a_hoff, const uint16_t* __restrict__ a_lidx
+#define CWENO_BIND_ARRAYS(p)                                                                           \
+  do {                                                                                                 \
+    p.q = a_q; p.out = a_out; p.sig = a_sig; p.om = a_om; p.pinv = a_pinv; p.binv = a_binv;            \
+    p.sigma = a_sigma; p.gidx = a_gidx; p.secpos = a_secpos; p.mask = a_mask; p.halo = a_halo;         \
+    p.hoff = a_hoff; p.lidx = a_lidx;                                                                  \
+  } while (0)
+#define CWENO_ARRAY_ARGS(p) \
+  p.q, p.out, p.sig, p.om, p.pinv, p.binv, p.sigma, p.gidx, p.secpos, p.mask, p.halo, p.hoff, p.lidx
+
 // Blocks are dispatched round-robin over the 8 XCDs; renumber them so that
 // each XCD sweeps one contiguous range of cells and the neighbour gathers of
 // consecutive blocks hit the same L2.
@@ -92,12 +110,6 @@ __host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / 
 template <typename T>
 __device__ __forceinline__ T ldo(const T* base, uint32_t byte_off) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
-}
-
-// LDS bytes a block needs to exchange P_opt rows (0 when RS == 1).
-template <int D, int M, int VB, int RS, typename T>
-__host__ __device__ constexpr int lds_bytes() {
-  return RS == 1 ? 0 : (kThreads / RS) * (nbasis_c(M, D) - 1) * VB * (int)sizeof(T);
 }
 
 // Sector differences Q_j - Q_i of variable v gathered from global memory.
@@ -214,81 +226,67 @@ __device__ __forceinline__ void finish_variable(const KParams<T>& p, int64_t i, 
   }
 }
 
-template <int D, int M, int VB, int RS, int KC, typename T>
-__global__ __launch_bounds__(kThreads) void reconstruct_kernel(KParams<T> p) {
+template <int D, int M, int VB, int KC, typename T>
+__global__ __launch_bounds__(kThreads) void reconstruct_kernel(KParams<T> p, CWENO_ARRAY_PARAMS(T)) {
+  CWENO_BIND_ARRAYS(p);
   constexpr int NB = nbasis_c(M, D);
   constexpr int NL = NB - 1;
   constexpr int NS = D + 1;
-  constexpr int NR = ceil_div(NL, RS);       // rows per lane (upper bound)
-  constexpr int CPB = kThreads / RS;         // cells per block
-  const int part = (int)threadIdx.x % RS;
-  const int cl = (int)threadIdx.x / RS;
-  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * CPB + cl;
-  if constexpr (RS == 1) {
-    if (i >= p.nc) return;
-  }
-  // Lanes past the last cell (RS > 1) work on the last cell and store nothing,
-  // so that every lane reaches the block barrier.
-  const bool valid = i < p.nc;
-  const int64_t ic = valid ? i : p.nc - 1;
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+  if (i >= p.nc) return;
   const int64_t Np = p.Np, qs = p.nc;
   const T* __restrict__ q = p.q + (int64_t)p.v0 * qs;
 
-  const uint32_t io = (uint32_t)ic * (uint32_t)sizeof(T);
-  const uint32_t io4 = (uint32_t)ic * 4u;
+  const uint32_t io = (uint32_t)i * (uint32_t)sizeof(T);
+  const uint32_t io4 = (uint32_t)i * 4u;
   T qi[VB];
 #pragma unroll
   for (int v = 0; v < VB; ++v) qi[v] = ldo(q + v * qs, io);
 
-  T acc[NR][VB];
+  T acc[NL][VB];
 #pragma unroll
-  for (int r = 0; r < NR; ++r)
+  for (int l = 0; l < NL; ++l)
 #pragma unroll
-    for (int v = 0; v < VB; ++v) acc[r][v] = T(0);
+    for (int v = 0; v < VB; ++v) acc[l][v] = T(0);
 
-  // (a) P_opt rows of this lane, stencil walked in chunks of KC
+  // (a) P_opt, stencil walked in chunks of KC
   const int NE1 = p.NE1;
   uint32_t gc[KC];
 #pragma unroll
   for (int kk = 0; kk < KC; ++kk)
-    gc[kk] = kk < NE1 ? (uint32_t)ldo(p.gidx + (int64_t)kk * Np, io4) : (uint32_t)ic;
+    gc[kk] = kk < NE1 ? (uint32_t)ldo(p.gidx + (int64_t)kk * Np, io4) : (uint32_t)i;
   for (int k0 = 0; k0 < NE1; k0 += KC) {
     uint32_t gn[KC];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
       const int k = k0 + KC + kk;
-      gn[kk] = k < NE1 ? (uint32_t)ldo(p.gidx + (int64_t)k * Np, io4) : (uint32_t)ic;
+      gn[kk] = k < NE1 ? (uint32_t)ldo(p.gidx + (int64_t)k * Np, io4) : (uint32_t)i;
     }
     T dq[KC][VB];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
 #pragma unroll
       for (int v = 0; v < VB; ++v) dq[kk][v] = ldo(q + v * qs, gc[kk] * (uint32_t)sizeof(T)) - qi[v];
-    T rr[KC][NR];
+    T rr[KC][NL];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
       const int k = k0 + kk;
       const T* __restrict__ row = p.pinv + (int64_t)k * NL * Np;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int l = part + r * RS;
-        rr[kk][r] = (l < NL && k < NE1)
-                        ? ldo(row, (uint32_t)(l * Np + ic) * (uint32_t)sizeof(T))
-                        : T(0);
-      }
+      for (int l = 0; l < NL; ++l) rr[kk][l] = k < NE1 ? ldo(row + (int64_t)l * Np, io) : T(0);
     }
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
+      for (int l = 0; l < NL; ++l)
 #pragma unroll
-        for (int v = 0; v < VB; ++v) acc[r][v] = fma(rr[kk][r], dq[kk][v], acc[r][v]);
+        for (int v = 0; v < VB; ++v) acc[l][v] = fma(rr[kk][l], dq[kk][v], acc[l][v]);
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) gc[kk] = gn[kk];
   }
 
   // Linear weights of this cell: dropped sectors get 0, the rest renormalised.
-  const unsigned mask = ldo(p.mask, (uint32_t)ic);
+  const unsigned mask = ldo(p.mask, (uint32_t)i);
   T lam[NS + 1];
   T lsum = p.lam[0];
   lam[0] = p.lam[0];
@@ -305,41 +303,14 @@ __global__ __launch_bounds__(kThreads) void reconstruct_kernel(KParams<T> p) {
   for (int s = 0; s < NS; ++s)
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const uint32_t pos = ldo(p.secpos + (s * D + a) * Np, (uint32_t)ic);
+      const uint32_t pos = ldo(p.secpos + (s * D + a) * Np, (uint32_t)i);
       sj[s][a] = ldo(p.gidx + (int64_t)pos * Np, io4);
     }
-
-  if constexpr (RS == 1) {
 #pragma unroll
-    for (int v = 0; v < VB; ++v) {
-      T dqs[NS][D];
-      sector_dq_global<D, T>(p, v, qi[v], sj, dqs);
-      finish_variable<D, M, T>(p, i, v, qi[v], [&](int l) { return acc[l][v]; }, lam, inv_l0, dqs);
-    }
-  } else {
-    // rows meet in LDS: [cell][l][v]
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    T* lds = reinterpret_cast<T*>(lds_raw) + (int64_t)cl * NL * VB;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const int l = part + r * RS;
-      if (l < NL) {
-#pragma unroll
-        for (int v = 0; v < VB; ++v) lds[l * VB + v] = acc[r][v];
-      }
-    }
-    __syncthreads();
-    if (!valid) return;
-#pragma unroll
-    for (int m = 0; m < ceil_div(VB, RS); ++m) {
-      const int v = part + m * RS;
-      if (v < VB) {
-        const T qv = ldo(q + (int64_t)v * qs, io);
-        T dqs[NS][D];
-        sector_dq_global<D, T>(p, v, qv, sj, dqs);
-        finish_variable<D, M, T>(p, i, v, qv, [&](int l) { return lds[l * VB + v]; }, lam, inv_l0, dqs);
-      }
-    }
+  for (int v = 0; v < VB; ++v) {
+    T dqs[NS][D];
+    sector_dq_global<D, T>(p, v, qi[v], sj, dqs);
+    finish_variable<D, M, T>(p, i, v, qi[v], [&](int l) { return acc[l][v]; }, lam, inv_l0, dqs);
   }
 }
 
