@@ -48,22 +48,26 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     if not os.path.exists(HIPCC):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
     os.makedirs(BUILD, exist_ok=True)
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    host_objs = [os.path.join(BUILD, src + ".o") for src in HOST_SOURCES]
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        list(ex.map(_run, [["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+                           for src, obj in zip(HOST_SOURCES, host_objs)]))
+    # the universal Sigma matrices become compile-time constants of the kernels
+    gen = os.path.join(BUILD, "gen_sigma")
+    _run(["g++", *HOST_FLAGS, "-o", gen, os.path.join(CSRC, "gen_sigma.cpp"), *host_objs])
+    _run([gen, os.path.join(BUILD, "sigma_tables.hpp")])
     cmds = []
-    objs = []
-    for src in HOST_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        cmds.append(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+    objs = list(host_objs)
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        cmds.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([HIPCC, *HIP_FLAGS, f"-I{BUILD}", "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for tn, d, m in KERNEL_UNITS:
         obj = os.path.join(BUILD, f"kernels_{tn}_d{d}_m{m}.o")
-        cmds.append([HIPCC, *HIP_FLAGS, f"-DCWENO_TN={tn}", f"-DCWENO_D={d}", f"-DCWENO_M={m}", "-c",
+        cmds.append([HIPCC, *HIP_FLAGS, f"-I{BUILD}", f"-DCWENO_TN={tn}", f"-DCWENO_D={d}", f"-DCWENO_M={m}", "-c",
                      os.path.join(CSRC, "kernels.hip"), "-o", obj])
         objs.append(obj)
-    jobs = jobs or min(16, os.cpu_count() or 4, len(cmds))
     with cf.ThreadPoolExecutor(jobs) as ex:
         for cmd, out in zip(cmds, ex.map(_run, cmds)):
             if verbose:

@@ -86,13 +86,16 @@ cweno_status upload_f32(DevBuf& b, const std::vector<double>& src, hipStream_t s
 bool variant_ok(const cweno_mesh* m, int vb, int k, bool f32) {
   const cweno::Variant& V = cweno::kVariants[k];
   if (!cweno::variant_allowed(m->d, m->M, vb, V, f32)) return false;
-  if (V.kind == 1) return m->maxH > 0 && (int64_t)m->maxH * vb * (f32 ? 4 : 8) <= cweno::kMaxLds;
+  // the halo kernel stages a block of vb variables through one 32-bit offset range
+  if (V.kind == 1)
+    return m->maxH > 0 && (int64_t)m->maxH * vb * (f32 ? 4 : 8) <= cweno::kMaxLds &&
+           (uint64_t)vb * (uint64_t)m->nc * (f32 ? 4u : 8u) < (uint64_t(1) << 32);
   return true;
 }
 
 // Default variant: the candidate order below, first one that can run.
 int default_variant(const cweno_mesh* m, int vb, bool f32) {
-  const int order[] = {3, 2, 4, 1, 0};
+  const int order[] = {3, 2, 4, 5, 6, 1, 0};
   for (int k : order)
     if (variant_ok(m, vb, k, f32)) return k;
   return -1;
@@ -154,9 +157,9 @@ cweno_status check_reconstruct_args(const cweno_mesh* m, int n_vars, cweno_dtype
   const bool f32 = dtype == CWENO_F32;
   if ((f32 && !m->pinv32.p) || (!f32 && !m->pinv64.p))
     return fail(CWENO_E_ARG, "the mesh holds no operators of this precision");
-  // neighbour averages are gathered with 32-bit byte offsets within one variable
-  if ((uint64_t)m->nc * (f32 ? 4u : 8u) >= (uint64_t(1) << 32))
-    return fail(CWENO_E_ARG, "too many cells for 32-bit offsets");
+  // averages are gathered, and the coefficients of a variable written, with 32-bit byte offsets
+  if ((uint64_t)m->nc * (uint64_t)m->nb * (f32 ? 4u : 8u) >= (uint64_t(1) << 32))
+    return fail(CWENO_E_ARG, "too many cells for 32-bit offsets within one variable's coefficients");
   // the kernels take every buffer as non-aliasing
   const uint64_t es = f32 ? 4 : 8, cells = (uint64_t)m->nc * (uint64_t)n_vars;
   const uint64_t nq = cells * es, nco = cells * (uint64_t)m->nb * es, nd = cells * (uint64_t)(m->d + 2) * es;
@@ -263,9 +266,13 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
   }
   m->G = m->op.G;
   m->Np = m->op.Np;
-  // the kernels address an operator row block and the averages with 32-bit byte offsets
-  if ((uint64_t)(m->nb - 1) * (uint64_t)m->Np * 8u >= (uint64_t(1) << 32))
-    return fail(CWENO_E_ARG, "mesh too large for one device operator block (split it)");
+  // the kernels address each block of operator or index rows with 32-bit byte offsets
+  {
+    const uint64_t Np = (uint64_t)m->Np, lim = uint64_t(1) << 32;
+    if ((uint64_t)(m->nb - 1) * Np * 8u >= lim || (uint64_t)(dim + 1) * dim * dim * Np * 8u >= lim ||
+        (uint64_t)(m->G + 1) * Np * 4u >= lim)
+      return fail(CWENO_E_ARG, "mesh too large for 32-bit offsets within an operator block (split it)");
+  }
   m->n_dropped = m->op.n_dropped;
 
   if (!(o.flags & CWENO_FLAG_HOST_ONLY)) {

@@ -9,10 +9,11 @@
 namespace cweno {
 
 // Kernel variants.  kind 0: reconstruct_kernel (neighbour averages gathered
-// from global memory); kind 1: reconstruct_halo_kernel (neighbour averages
-// from the block's LDS halo).  kc: stencil entries per chunk.
-struct Variant { int kind, kc; };
-constexpr Variant kVariants[] = {{0, 1}, {0, 2}, {1, 1}, {1, 2}, {1, 4}};
+// from global memory), kc stencil entries per chunk.  kind 1:
+// reconstruct_halo_kernel (neighbour averages from the block's LDS halo), kc
+// stencil entries per chunk, halo staged hu entries per thread at a time.
+struct Variant { int kind, kc, hu; };
+constexpr Variant kVariants[] = {{0, 1, 0}, {0, 2, 0}, {1, 1, 4}, {1, 2, 4}, {1, 2, 2}, {1, 2, 8}, {1, 4, 4}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 // Variable-block sizes that are instantiated.  A lane keeps (n_basis-1) * VB

@@ -3,7 +3,7 @@
 // Same arithmetic as reconstruct_kernel (one lane per cell; each P_opt row a
 // FMA chain over the stencil in order k = 0, 1, ...; identical epilogue).
 //
-// Neighbour gathers are what limits the direct kernels: every stencil entry
+// Neighbour gathers are what limits the direct kernel: every stencil entry
 // of 64 lanes is a scattered load, and the texture-data return path spends
 // far longer on it than on a coalesced operator row.  Consecutive cells share
 // most of their stencil cells, so a workgroup of 256 consecutive cells first
@@ -13,7 +13,12 @@
 // through 16-bit halo positions.  The operator rows keep streaming from HBM
 // in coalesced loads; the 16-bit positions also halve the index stream.
 //
-// LDS layout: halo values [VB][maxH].
+// The halo is staged HU entries per thread at a time (all index loads, then
+// all value loads, then the LDS stores), and the operator rows of the first
+// KC stencil entries are requested before the workgroup barrier.
+//
+// LDS layout: halo values [maxH][VB] (the VB averages of a halo cell
+// together, so one address per stencil entry serves every variable).
 #pragma once
 
 #include "reconstruct_kernel.hpp"
@@ -22,7 +27,50 @@ namespace cweno {
 
 constexpr int kHaloBlock = 256;   // cells (and threads) per workgroup; fixed by the host's halo lists
 
-template <int D, int M, int VB, int KC, typename T>
+template <int NL, int KC, typename T>
+__device__ __forceinline__ void load_rows(T (&r)[KC][NL], const T* pinv, int64_t Np, int NE1, int k0,
+                                          uint32_t io) {
+  const uint32_t prow = (uint32_t)Np * (uint32_t)sizeof(T);
+#pragma unroll
+  for (int kk = 0; kk < KC; ++kk) {
+    const int k = k0 + kk;
+    const rsrc_t rk = make_rsrc(pinv + (int64_t)k * NL * Np, NL * prow);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) r[kk][l] = k < NE1 ? bld<T>(rk, io, (uint32_t)l * prow) : T(0);
+  }
+}
+
+// Halo positions of stencil entries k0 .. k0+KC-1; entries past the stencil
+// point at the cell itself, so that their differences are exactly zero.
+template <int KC>
+__device__ __forceinline__ void load_pos(uint32_t (&h)[KC], rsrc_t rl, uint32_t lrow, int NE1, int k0, uint32_t io2,
+                                         uint32_t self) {
+#pragma unroll
+  for (int kk = 0; kk < KC; ++kk) {
+    const int k = k0 + kk;
+    h[kk] = k < NE1 ? (uint32_t)bld<uint16_t>(rl, io2, (uint32_t)k * lrow) : self;
+  }
+}
+
+// acc[l][v] += r[kk][l] * (Q_{j(k)} - Q_i) for the KC entries of one chunk
+// (entries past the stencil have zero rows and zero differences)
+template <int NL, int VB, int KC, typename T>
+__device__ __forceinline__ void fma_chunk(T (&acc)[NL][VB], const T (&r)[KC][NL], const uint32_t (&h)[KC],
+                                          const T* lq, uint32_t self) {
+#pragma unroll
+  for (int kk = 0; kk < KC; ++kk) {
+    const T* hv = lq + h[kk] * VB;
+    const T* sv = lq + self * VB;
+#pragma unroll
+    for (int v = 0; v < VB; ++v) {
+      const T dq = hv[v] - sv[v];
+#pragma unroll
+      for (int l = 0; l < NL; ++l) acc[l][v] = fma(r[kk][l], dq, acc[l][v]);
+    }
+  }
+}
+
+template <int D, int M, int VB, int KC, int HU, typename T>
 __global__ __launch_bounds__(kHaloBlock) void reconstruct_halo_kernel(KParams<T> p, CWENO_ARRAY_PARAMS(T)) {
   CWENO_BIND_ARRAYS(p);
   constexpr int NB = nbasis_c(M, D);
@@ -37,31 +85,58 @@ __global__ __launch_bounds__(kHaloBlock) void reconstruct_halo_kernel(KParams<T>
   const bool valid = i < p.nc;
   const int64_t ic = valid ? i : p.nc - 1;
   const int64_t Np = p.Np, qs = p.nc;
-  const int maxH = p.maxH;
-  const T* __restrict__ q = p.q + (int64_t)p.v0 * qs;
+  const int NE1 = p.NE1;
   const uint32_t io = (uint32_t)ic * (uint32_t)sizeof(T);
   const uint32_t io2 = (uint32_t)ic * 2u;
-  (void)io;
+  const uint32_t lrow = (uint32_t)Np * 2u;
+  const rsrc_t rl = make_rsrc(p.lidx, (uint32_t)(p.G + 1) * lrow);
+  const rsrc_t rq = make_rsrc(p.q + (int64_t)p.v0 * qs, (uint32_t)VB * (uint32_t)qs * (uint32_t)sizeof(T));
+  const uint32_t qrow = (uint32_t)qs * (uint32_t)sizeof(T);
 
-  // stage the block's halo averages
+  // stage the block's halo averages, HU entries per thread at a time
   const int h0 = p.hoff[b], hn = p.hoff[b + 1] - h0;
-  for (int t = tid; t < hn; t += kHaloBlock) {
-    const uint32_t j = (uint32_t)p.halo[h0 + t];
+  const rsrc_t rh = make_rsrc(p.halo + h0, (uint32_t)hn * 4u);
+  for (int t0 = 0; t0 < hn; t0 += HU * kHaloBlock) {
+    uint32_t j[HU];
 #pragma unroll
-    for (int v = 0; v < VB; ++v) lq[v * maxH + t] = ldo(q + v * qs, j * (uint32_t)sizeof(T));
+    for (int u = 0; u < HU; ++u) {
+      const int t = t0 + u * kHaloBlock + tid;
+      j[u] = t < hn ? (uint32_t)bld<int32_t>(rh, (uint32_t)t * 4u, 0u) : 0u;
+    }
+    T val[HU][VB];
+#pragma unroll
+    for (int u = 0; u < HU; ++u)
+#pragma unroll
+      for (int v = 0; v < VB; ++v) val[u][v] = bld<T>(rq, j[u] * (uint32_t)sizeof(T), (uint32_t)v * qrow);
+#pragma unroll
+    for (int u = 0; u < HU; ++u) {
+      const int t = t0 + u * kHaloBlock + tid;
+      if (t < hn) {
+#pragma unroll
+        for (int v = 0; v < VB; ++v) lq[t * VB + v] = val[u][v];
+      }
+    }
   }
 
   // the cell itself is in its block's halo: its averages are read from LDS when needed
-  const uint32_t self = ldo(p.lidx + (int64_t)p.G * Np, io2);
+  const uint32_t self = bld<uint16_t>(rl, io2, (uint32_t)p.G * lrow);
+  const rsrc_t rsp = make_rsrc(p.secpos, (uint32_t)(NS * D) * (uint32_t)Np);
   uint32_t sl[NS][D];     // halo positions of the sector cells
 #pragma unroll
   for (int s = 0; s < NS; ++s)
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const uint32_t pos = ldo(p.secpos + (s * D + a) * Np, (uint32_t)ic);
-      sl[s][a] = ldo(p.lidx + (int64_t)pos * Np, io2);
+      const uint32_t pos = bld<uint8_t>(rsp, (uint32_t)ic, (uint32_t)(s * D + a) * (uint32_t)Np);
+      sl[s][a] = bld<uint16_t>(rl, io2, pos * lrow);
     }
   const unsigned mask = ldo(p.mask, (uint32_t)ic);
+
+  // (a) P_opt, stencil walked in chunks of KC entries; the first chunk's rows
+  // and positions are requested before the barrier
+  T rr[KC][NL];
+  uint32_t hc[KC];
+  load_rows<NL, KC, T>(rr, p.pinv, Np, NE1, 0, io);
+  load_pos<KC>(hc, rl, lrow, NE1, 0, io2, self);
   __syncthreads();
 
   T acc[NL][VB];
@@ -70,63 +145,31 @@ __global__ __launch_bounds__(kHaloBlock) void reconstruct_halo_kernel(KParams<T>
 #pragma unroll
     for (int v = 0; v < VB; ++v) acc[l][v] = T(0);
 
-  // (a) P_opt, stencil walked in chunks of KC; positions of the next chunk prefetched
-  const int NE1 = p.NE1;
-  uint32_t hc[KC];
-#pragma unroll
-  for (int kk = 0; kk < KC; ++kk) hc[kk] = kk < NE1 ? (uint32_t)ldo(p.lidx + (int64_t)kk * Np, io2) : 0u;
-  for (int k0 = 0; k0 < NE1; k0 += KC) {
-    uint32_t hn_[KC];
-#pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      const int k = k0 + KC + kk;
-      hn_[kk] = k < NE1 ? (uint32_t)ldo(p.lidx + (int64_t)k * Np, io2) : 0u;
-    }
-    T rr[KC][NL];
-#pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      const int k = k0 + kk;
-      const T* __restrict__ row = p.pinv + (int64_t)k * NL * Np;
-#pragma unroll
-      for (int l = 0; l < NL; ++l)
-        rr[kk][l] = k < NE1 ? ldo(row + (int64_t)l * Np, io) : T(0);
-    }
-#pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      T dq[VB];
-#pragma unroll
-      for (int v = 0; v < VB; ++v) dq[v] = lq[v * maxH + hc[kk]] - lq[v * maxH + self];
-#pragma unroll
-      for (int l = 0; l < NL; ++l)
-#pragma unroll
-        for (int v = 0; v < VB; ++v) acc[l][v] = fma(rr[kk][l], dq[v], acc[l][v]);
-    }
-#pragma unroll
-    for (int kk = 0; kk < KC; ++kk) hc[kk] = hn_[kk];
+  fma_chunk<NL, VB, KC, T>(acc, rr, hc, lq, self);
+  for (int k0 = KC; k0 < NE1; k0 += KC) {
+    load_rows<NL, KC, T>(rr, p.pinv, Np, NE1, k0, io);
+    load_pos<KC>(hc, rl, lrow, NE1, k0, io2, self);
+    fma_chunk<NL, VB, KC, T>(acc, rr, hc, lq, self);
   }
 
-  // Linear weights of this cell: dropped sectors get 0, the rest renormalised.
   T lam[NS + 1];
-  T lsum = p.lam[0];
-  lam[0] = p.lam[0];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    lam[s + 1] = ((mask >> s) & 1u) ? p.lam[s + 1] : T(0);
-    lsum += lam[s + 1];
-  }
-#pragma unroll
-  for (int s = 0; s <= NS; ++s) lam[s] /= lsum;
-  const T inv_l0 = T(1) / lam[0];
+  const T inv_l0 = cell_weights<NS, T>(p, mask, lam);
   if (!valid) return;
+  T bv[NS][D][D];
+  load_binv<D, T>(p.binv, Np, io, bv);
+  const T* sv = lq + self * VB;
 #pragma unroll
   for (int v = 0; v < VB; ++v) {
-    const T qi = lq[v * maxH + self];
+    const T qi = sv[v];
     T dqs[NS][D];
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
-      for (int a = 0; a < D; ++a) dqs[s][a] = lq[v * maxH + sl[s][a]] - qi;
-    finish_variable<D, M, T>(p, i, v, qi, [&](int l) { return acc[l][v]; }, lam, inv_l0, dqs);
+      for (int a = 0; a < D; ++a) dqs[s][a] = lq[sl[s][a] * VB + v] - qi;
+    T po[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) po[l] = acc[l][v];
+    finish_variable<D, M, T>(p, io, v, qi, po, lam, inv_l0, dqs, bv);
   }
 }
 

@@ -36,13 +36,13 @@ hipError_t launch_direct(const KParams<real_t>& p, hipStream_t s) {
   }
 }
 
-template <int VB, int KC>
+template <int VB, int KC, int HU>
 hipError_t launch_halo(const KParams<real_t>& p, hipStream_t s) {
   if constexpr (vb_allowed(CWENO_D, CWENO_M, VB, sizeof(real_t) == 4)) {
     const int64_t blocks = (p.nc + kHaloBlock - 1) / kHaloBlock;
     const size_t lds = (size_t)p.maxH * VB * sizeof(real_t);
     if (p.maxH <= 0 || lds > (size_t)kMaxLds) return hipErrorInvalidValue;
-    auto fn = reconstruct_halo_kernel<CWENO_D, CWENO_M, VB, KC, real_t>;
+    auto fn = reconstruct_halo_kernel<CWENO_D, CWENO_M, VB, KC, HU, real_t>;
     if (lds > 65536) {
       hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
@@ -59,9 +59,11 @@ hipError_t launch_variant(const KParams<real_t>& p, int k, hipStream_t s) {
   switch (k) {
     case 0: return launch_direct<VB, 1>(p, s);
     case 1: return launch_direct<VB, 2>(p, s);
-    case 2: return launch_halo<VB, 1>(p, s);
-    case 3: return launch_halo<VB, 2>(p, s);
-    case 4: return launch_halo<VB, 4>(p, s);
+    case 2: return launch_halo<VB, 1, 4>(p, s);
+    case 3: return launch_halo<VB, 2, 4>(p, s);
+    case 4: return launch_halo<VB, 2, 2>(p, s);
+    case 5: return launch_halo<VB, 2, 8>(p, s);
+    case 6: return launch_halo<VB, 4, 4>(p, s);
     default: return hipErrorInvalidValue;
   }
 }

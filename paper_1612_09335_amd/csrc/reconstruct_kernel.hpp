@@ -24,13 +24,21 @@
 //   gidx[k * Np + i] (int32)        k < G: stencil cells then sector extras
 //   secpos[(s * D + a) * Np + i] (uint8), mask[i] (uint8, bit s = sector alive)
 //   q[v * qs + i], out[(v * NB + l) * qs + i] with qs = n_cells
-// so the lanes of a wavefront read contiguous runs.  Every load
-// is a wave-uniform base (scalar registers) plus a 32-bit per-lane byte
-// offset; the host guarantees that the offsets fit (rows of at most 4 GiB).
+// so the lanes of a wavefront read contiguous runs.
+//
+// Addressing.  The operator rows, index rows and coefficient rows are read and
+// written through buffer resources: a wave-uniform 64-bit base in scalar
+// registers, a wave-uniform row offset in a scalar register and the lane's
+// 32-bit byte offset, so that no vector instruction is spent on addresses.
+// The host guarantees that every such offset fits in 32 bits.  The universal
+// Sigma of (D, M) is a table of compile-time constants (generated at build
+// time), folded into the instructions.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "sigma_tables.hpp"   // generated at build time by gen_sigma.cpp
 
 namespace cweno {
 
@@ -71,9 +79,8 @@ struct KParams {
 // Every array also reaches a kernel as an argument of its own, marked
 // __restrict__: the arrays never overlap (the library rejects overlapping
 // caller buffers), and saying so lets the compiler keep the sector operators
-// in registers and read the universal Sigma through the scalar cache instead
-// of reloading both after every store of a coefficient.  A kernel rebinds the
-// fields of its KParams to these arguments on entry.
+// in registers instead of reloading them after every store of a coefficient.
+// A kernel rebinds the fields of its KParams to these arguments on entry.
 #define CWENO_ARRAY_PARAMS(T)                                                                          \
   const T* __restrict__ a_q, T* __restrict__ a_out, T* __restrict__ a_sig, T* __restrict__ a_om,       \
       const T* __restrict__ a_pinv, const T* __restrict__ a_binv, const T* __restrict__ a_sigma,       \
@@ -89,6 +96,49 @@ struct KParams {
 #define CWENO_ARRAY_ARGS(p) \
   p.q, p.out, p.sig, p.om, p.pinv, p.binv, p.sigma, p.gidx, p.secpos, p.mask, p.halo, p.hoff, p.lidx
 
+// ---------------------------------------------------------------- addressing
+
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Raw buffer resource over `bytes` bytes from `base` (gfx9 word 3: 32-bit
+// untyped data, no swizzle).
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// Load/store at byte offset voff (per lane) + soff (wave-uniform).
+template <typename T> __device__ __forceinline__ T bld(rsrc_t r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ double bld<double>(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ float bld<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ int32_t bld<int32_t>(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+}
+template <> __device__ __forceinline__ uint16_t bld<uint16_t>(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+}
+template <> __device__ __forceinline__ uint8_t bld<uint8_t>(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b8(r, voff, soff, 0);
+}
+__device__ __forceinline__ void bst(rsrc_t r, double x, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bst(rsrc_t r, float x, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, voff, soff, 0);
+}
+
+// Load from a wave-uniform base plus a 32-bit per-lane byte offset (gathers).
+template <typename T>
+__device__ __forceinline__ T ldo(const T* base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+// ---------------------------------------------------------------- helpers
+
 // Blocks are dispatched round-robin over the 8 XCDs; renumber them so that
 // each XCD sweeps one contiguous range of cells and the neighbour gathers of
 // consecutive blocks hit the same L2.
@@ -97,80 +147,133 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
   return x * q + (x < r ? x : r) + k;
 }
 
-template <typename T>
-__device__ __forceinline__ T powi(T x, int r) {
-  T y = x;
-  for (int t = 1; t < r; ++t) y *= x;
-  return y;
+// x[s]^r for the wave-uniform exponent r >= 1; r = 4 (the usual choice)
+// without a loop.
+template <int N, typename T>
+__device__ __forceinline__ void powi(T (&x)[N], int r) {
+  if (r == 4) {
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+      const T x2 = x[s] * x[s];
+      x[s] = x2 * x2;
+    }
+    return;
+  }
+  T y[N];
+#pragma unroll
+  for (int s = 0; s < N; ++s) y[s] = x[s];
+  for (int t = 1; t < r; ++t)
+#pragma unroll
+    for (int s = 0; s < N; ++s) y[s] *= x[s];
+#pragma unroll
+  for (int s = 0; s < N; ++s) x[s] = y[s];
 }
 
 __host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// Load from a wave-uniform base plus a 32-bit per-lane byte offset.
-template <typename T>
-__device__ __forceinline__ T ldo(const T* base, uint32_t byte_off) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+// 1/x for finite x > 0 whose reciprocal is a normal number: the hardware
+// estimate refined by Newton steps e = 1 - x r, r += r e (one step in single
+// precision, two in double), within an ulp or two of the rounded quotient.
+__device__ __forceinline__ float rcp_pos(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double rcp_pos(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
 }
 
-// Sector differences Q_j - Q_i of variable v gathered from global memory.
+// p^T Sigma p over coefficients 1..NL with the universal Sigma of (D, M) as
+// compile-time constants (symmetric: each off-diagonal product once, doubled).
+template <int D, int M, typename T>
+__device__ __forceinline__ T quad_form(const T (&pv)[nbasis_c(M, D) - 1]) {
+  constexpr int NL = nbasis_c(M, D) - 1;
+  using S = SigmaTable<D, M>;
+  T x = T(0);
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    T y = T(0);
+#pragma unroll
+    for (int m = l + 1; m < NL; ++m) y = fma(T(S::v[l * NL + m]), pv[m], y);
+    x = fma(pv[l], fma(T(2), y, T(S::v[l * NL + l]) * pv[l]), x);
+  }
+  return x;
+}
+
+// Per-cell linear weights: dropped sectors (mask bit clear) get 0, the rest
+// are renormalised; returns 1 / lambda_0.
+template <int NS, typename T>
+__device__ __forceinline__ T cell_weights(const KParams<T>& p, unsigned mask, T (&lam)[NS + 1]) {
+  T lsum = p.lam[0];
+  lam[0] = p.lam[0];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    lam[s + 1] = ((mask >> s) & 1u) ? p.lam[s + 1] : T(0);
+    lsum += lam[s + 1];
+  }
+#pragma unroll
+  for (int s = 0; s <= NS; ++s) lam[s] /= lsum;
+  return T(1) / lam[0];
+}
+
+// The cell's sector operators binv[s][l][a] (loaded once for all variables,
+// before the first coefficient store).
 template <int D, typename T>
-__device__ __forceinline__ void sector_dq_global(const KParams<T>& p, int v, T qi, const int32_t (&sj)[D + 1][D],
-                                                 T (&dqs)[D + 1][D]) {
-  const T* __restrict__ q = p.q + (int64_t)(p.v0 + v) * p.nc;
+__device__ __forceinline__ void load_binv(const T* binv, int64_t Np, uint32_t io, T (&bv)[D + 1][D][D]) {
+  const uint32_t prow = (uint32_t)Np * (uint32_t)sizeof(T);
+  const rsrc_t rb = make_rsrc(binv, (uint32_t)((D + 1) * D * D) * prow);
 #pragma unroll
   for (int s = 0; s <= D; ++s)
 #pragma unroll
-    for (int a = 0; a < D; ++a) dqs[s][a] = ldo(q, (uint32_t)sj[s][a] * (uint32_t)sizeof(T)) - qi;
+    for (int l = 0; l < D; ++l)
+#pragma unroll
+      for (int a = 0; a < D; ++a) bv[s][l][a] = bld<T>(rb, io, (uint32_t)((s * D + l) * D + a) * prow);
 }
 
 // Steps (b)-(e) for one cell and one variable, given P_opt's coefficients
-// 1..NB-1 as popt(l) and the sector differences dqs[s][a] = Q_{j^s(a)} - Q_i.
-template <int D, int M, typename T, class PoptFn>
-__device__ __forceinline__ void finish_variable(const KParams<T>& p, int64_t i, int v, T qi, PoptFn popt,
-                                                const T (&lam)[D + 2], T inv_l0, const T (&dqs)[D + 1][D]) {
+// 1..NB-1 in po (overwritten) and the sector differences
+// dqs[s][a] = Q_{j^s(a)} - Q_i.  lam holds the cell's linear weights
+// (normalised), inv_l0 = 1 / lam[0].  io is the lane's byte offset of its
+// cell in an operator or coefficient row.
+template <int D, int M, typename T>
+__device__ __forceinline__ void finish_variable(const KParams<T>& p, uint32_t io, int v, T qi,
+                                                T (&po)[nbasis_c(M, D) - 1], const T (&lam)[D + 2], T inv_l0,
+                                                const T (&dqs)[D + 1][D], const T (&bv)[D + 1][D][D]) {
   constexpr int NB = nbasis_c(M, D);
   constexpr int NL = NB - 1;
   constexpr int NS = D + 1;
   const int64_t qs = p.nc, Np = p.Np;
-  const uint32_t io = (uint32_t)i * (uint32_t)sizeof(T);
+  const uint32_t prow = (uint32_t)Np * (uint32_t)sizeof(T);   // operator row, bytes
+  const uint32_t crow = (uint32_t)qs * (uint32_t)sizeof(T);   // coefficient row, bytes
   // (b) sectorial P1 polynomials
   T ps[NS][D];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
+  for (int s = 0; s < NS; ++s)
 #pragma unroll
     for (int l = 0; l < D; ++l) {
       T x = T(0);
 #pragma unroll
-      for (int a = 0; a < D; ++a) x = fma(ldo(p.binv + ((s * D + l) * D + a) * Np, io), dqs[s][a], x);
+      for (int a = 0; a < D; ++a) x = fma(bv[s][l][a], dqs[s][a], x);
       ps[s][l] = x;
     }
-  }
-  // (c) P_0
-  T p0[NL];
+  // (c) P_0 = u / lambda_0 with u = P_opt - sum_s lambda_s P_s; only the
+  // linear coefficients differ from P_opt's.  (d) oscillation indicators,
+  // sigma(P_0) = sigma(u) / lambda_0^2 (or sigma(P_opt) on request).
+  const bool s_popt = p.sigma0_popt;
+  T u[D];
 #pragma unroll
-  for (int l = 0; l < NL; ++l) {
-    T x = popt(l);
-    if (l < D) {
+  for (int l = 0; l < D; ++l) {
+    T x = po[l];
 #pragma unroll
-      for (int s = 0; s < NS; ++s) x = fma(-lam[s + 1], ps[s][l], x);
-    }
-    p0[l] = x * inv_l0;
+    for (int s = 0; s < NS; ++s) x = fma(-lam[s + 1], ps[s][l], x);
+    u[l] = x;
+    po[l] = s_popt ? po[l] : x;
   }
-  // (d) oscillation indicators (Sigma is symmetric)
-  const T* __restrict__ Sg = p.sigma;
   T sg[NS + 1];
-  {
-    T x = T(0);
+  sg[0] = quad_form<D, M, T>(po) * (s_popt ? T(1) : inv_l0 * inv_l0);
 #pragma unroll
-    for (int l = 0; l < NL; ++l) {
-      const T pl = p.sigma0_popt ? popt(l) : p0[l];
-      T y = T(0);
-#pragma unroll
-      for (int m = l + 1; m < NL; ++m) y = fma(Sg[l * NL + m], p.sigma0_popt ? popt(m) : p0[m], y);
-      x = fma(pl, fma(T(2), y, Sg[l * NL + l] * pl), x);
-    }
-    sg[0] = x;
-  }
+  for (int l = 0; l < D; ++l) po[l] = u[l];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     T x = T(0);
@@ -178,53 +281,63 @@ __device__ __forceinline__ void finish_variable(const KParams<T>& p, int64_t i, 
     for (int l = 0; l < D; ++l) {
       T y = T(0);
 #pragma unroll
-      for (int m = l + 1; m < D; ++m) y = fma(Sg[l * NL + m], ps[s][m], y);
-      x = fma(ps[s][l], fma(T(2), y, Sg[l * NL + l] * ps[s][l]), x);
+      for (int m = l + 1; m < D; ++m) y = fma(T(SigmaTable<D, M>::v[l * NL + m]), ps[s][m], y);
+      x = fma(ps[s][l], fma(T(2), y, T(SigmaTable<D, M>::v[l * NL + l]) * ps[s][l]), x);
     }
     sg[s + 1] = x;
   }
-  // (e) nonlinear weights and blend
+  // (e) nonlinear weights lambda_s (m_min / m_s)^r normalised, m_s = sigma_s + eps
   T om[NS + 1];
   if (p.linear_w) {
 #pragma unroll
     for (int s = 0; s <= NS; ++s) om[s] = lam[s];
   } else {
-    T dmin = sg[0] + p.eps;
+    T ms[NS + 1];
+#pragma unroll
+    for (int s = 0; s <= NS; ++s) ms[s] = sg[s] + p.eps;
+    T mmin = ms[0];
 #pragma unroll
     for (int s = 1; s <= NS; ++s)
-      if (lam[s] > T(0)) dmin = fmin(dmin, sg[s] + p.eps);
+      if (lam[s] > T(0)) mmin = fmin(mmin, ms[s]);
+#pragma unroll
+    for (int s = 0; s <= NS; ++s) om[s] = mmin * rcp_pos(ms[s]);
+    powi<NS + 1, T>(om, p.r);
     T tot = T(0);
 #pragma unroll
     for (int s = 0; s <= NS; ++s) {
-      om[s] = lam[s] * powi(dmin / (sg[s] + p.eps), p.r);
+      om[s] *= lam[s];
       tot += om[s];
     }
-    const T inv = T(1) / tot;
+    const T inv = rcp_pos(tot);
 #pragma unroll
     for (int s = 0; s <= NS; ++s) om[s] *= inv;
   }
-  T* o = p.out + (int64_t)(p.v0 + v) * NB * qs + i;
-  o[0] = qi;
+  // blend: w = omega_0 P_0 + sum_s omega_s P_s; coefficient 0 is Q_i itself
+  const rsrc_t ro = make_rsrc(p.out + (int64_t)(p.v0 + v) * NB * qs, NB * crow);
+  bst(ro, qi, io, 0u);
+  const T c0 = om[0] * inv_l0;
 #pragma unroll
   for (int l = 0; l < NL; ++l) {
-    T x = om[0] * p0[l];
+    T x = c0 * po[l];
     if (l < D) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) x = fma(om[s + 1], ps[s][l], x);
+      for (int s = 0; s < NS; ++s) x = fma(om[s + 1], ps[s][l < D ? l : 0], x);
     }
-    o[(int64_t)(l + 1) * qs] = x;
+    bst(ro, x, io, (uint32_t)(l + 1) * crow);
   }
   if (p.sig) {
-    T* so = p.sig + ((int64_t)(p.v0 + v) * (NS + 1)) * qs + i;
+    const rsrc_t rs = make_rsrc(p.sig + (int64_t)(p.v0 + v) * (NS + 1) * qs, (NS + 1) * crow);
 #pragma unroll
-    for (int s = 0; s <= NS; ++s) so[(int64_t)s * qs] = sg[s];
+    for (int s = 0; s <= NS; ++s) bst(rs, sg[s], io, (uint32_t)s * crow);
   }
   if (p.om) {
-    T* oo = p.om + ((int64_t)(p.v0 + v) * (NS + 1)) * qs + i;
+    const rsrc_t rw = make_rsrc(p.om + (int64_t)(p.v0 + v) * (NS + 1) * qs, (NS + 1) * crow);
 #pragma unroll
-    for (int s = 0; s <= NS; ++s) oo[(int64_t)s * qs] = om[s];
+    for (int s = 0; s <= NS; ++s) bst(rw, om[s], io, (uint32_t)s * crow);
   }
 }
+
+// ---------------------------------------------------------------- direct kernel
 
 template <int D, int M, int VB, int KC, typename T>
 __global__ __launch_bounds__(kThreads) void reconstruct_kernel(KParams<T> p, CWENO_ARRAY_PARAMS(T)) {
@@ -236,9 +349,12 @@ __global__ __launch_bounds__(kThreads) void reconstruct_kernel(KParams<T> p, CWE
   if (i >= p.nc) return;
   const int64_t Np = p.Np, qs = p.nc;
   const T* __restrict__ q = p.q + (int64_t)p.v0 * qs;
+  const uint32_t prow = (uint32_t)Np * (uint32_t)sizeof(T);
+  const uint32_t irow = (uint32_t)Np * 4u;
 
   const uint32_t io = (uint32_t)i * (uint32_t)sizeof(T);
   const uint32_t io4 = (uint32_t)i * 4u;
+  const rsrc_t rg = make_rsrc(p.gidx, (uint32_t)p.G * irow);
   T qi[VB];
 #pragma unroll
   for (int v = 0; v < VB; ++v) qi[v] = ldo(q + v * qs, io);
@@ -254,13 +370,13 @@ __global__ __launch_bounds__(kThreads) void reconstruct_kernel(KParams<T> p, CWE
   uint32_t gc[KC];
 #pragma unroll
   for (int kk = 0; kk < KC; ++kk)
-    gc[kk] = kk < NE1 ? (uint32_t)ldo(p.gidx + (int64_t)kk * Np, io4) : (uint32_t)i;
+    gc[kk] = kk < NE1 ? (uint32_t)bld<int32_t>(rg, io4, (uint32_t)kk * irow) : (uint32_t)i;
   for (int k0 = 0; k0 < NE1; k0 += KC) {
     uint32_t gn[KC];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
       const int k = k0 + KC + kk;
-      gn[kk] = k < NE1 ? (uint32_t)ldo(p.gidx + (int64_t)k * Np, io4) : (uint32_t)i;
+      gn[kk] = k < NE1 ? (uint32_t)bld<int32_t>(rg, io4, (uint32_t)k * irow) : (uint32_t)i;
     }
     T dq[KC][VB];
 #pragma unroll
@@ -271,9 +387,9 @@ __global__ __launch_bounds__(kThreads) void reconstruct_kernel(KParams<T> p, CWE
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
       const int k = k0 + kk;
-      const T* __restrict__ row = p.pinv + (int64_t)k * NL * Np;
+      const rsrc_t rk = make_rsrc(p.pinv + (int64_t)k * NL * Np, NL * prow);
 #pragma unroll
-      for (int l = 0; l < NL; ++l) rr[kk][l] = k < NE1 ? ldo(row + (int64_t)l * Np, io) : T(0);
+      for (int l = 0; l < NL; ++l) rr[kk][l] = k < NE1 ? bld<T>(rk, io, (uint32_t)l * prow) : T(0);
     }
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
@@ -285,32 +401,32 @@ __global__ __launch_bounds__(kThreads) void reconstruct_kernel(KParams<T> p, CWE
     for (int kk = 0; kk < KC; ++kk) gc[kk] = gn[kk];
   }
 
-  // Linear weights of this cell: dropped sectors get 0, the rest renormalised.
+  const rsrc_t rsp = make_rsrc(p.secpos, (uint32_t)(NS * D) * (uint32_t)Np);
   const unsigned mask = ldo(p.mask, (uint32_t)i);
   T lam[NS + 1];
-  T lsum = p.lam[0];
-  lam[0] = p.lam[0];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    lam[s + 1] = ((mask >> s) & 1u) ? p.lam[s + 1] : T(0);
-    lsum += lam[s + 1];
-  }
-#pragma unroll
-  for (int s = 0; s <= NS; ++s) lam[s] /= lsum;
-  const T inv_l0 = T(1) / lam[0];
+  const T inv_l0 = cell_weights<NS, T>(p, mask, lam);
   int32_t sj[NS][D];
 #pragma unroll
   for (int s = 0; s < NS; ++s)
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const uint32_t pos = ldo(p.secpos + (s * D + a) * Np, (uint32_t)i);
-      sj[s][a] = ldo(p.gidx + (int64_t)pos * Np, io4);
+      const uint32_t pos = bld<uint8_t>(rsp, (uint32_t)i, (uint32_t)(s * D + a) * (uint32_t)Np);
+      sj[s][a] = bld<int32_t>(rg, io4, pos * irow);
     }
+  T bv[NS][D][D];
+  load_binv<D, T>(p.binv, Np, io, bv);
 #pragma unroll
   for (int v = 0; v < VB; ++v) {
+    const T* __restrict__ qv = q + v * qs;
     T dqs[NS][D];
-    sector_dq_global<D, T>(p, v, qi[v], sj, dqs);
-    finish_variable<D, M, T>(p, i, v, qi[v], [&](int l) { return acc[l][v]; }, lam, inv_l0, dqs);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int a = 0; a < D; ++a) dqs[s][a] = ldo(qv, (uint32_t)sj[s][a] * (uint32_t)sizeof(T)) - qi[v];
+    T po[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) po[l] = acc[l][v];
+    finish_variable<D, M, T>(p, io, v, qi[v], po, lam, inv_l0, dqs, bv);
   }
 }
 
