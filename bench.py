@@ -7,7 +7,10 @@ ratio 10).  One step = one cweno_reconstruct of the whole mesh (all five steps
 of the method for every cell and variable), inputs already resident in HBM.
 
 Prints one JSON line.  ``value`` is the FP64 path's cells*vars/s; the FP32
-operator path is reported beside it under "fp32".
+operator path is reported beside it under "fp32".  Unless --quick is given,
+two more workloads are measured and reported under "extras": the small 2-D
+M=2 mesh (8,192 triangles, 4 Euler variables) as launch latency p50/p99, and
+the 3-D M=3 mesh (1,572,864 Kuhn tetrahedra, 5 variables) as throughput.
 """
 from __future__ import annotations
 
@@ -26,27 +29,34 @@ sys.path.insert(0, ROOT)
 METRIC = "CWENO cells·vars reconstructed/s + % HBM peak, FP64 vs FP32; p99 latency"
 HBM_PEAK_GBS = 8000.0
 SEED = 16120935
-KERNEL_SRC = os.path.join(ROOT, "paper_1612_09335_amd", "csrc", "reconstruct_kernel.hpp")
+CSRC = os.path.join(ROOT, "paper_1612_09335_amd", "csrc")
+KERNEL_SRCS = ["reconstruct_kernel.hpp", "halo_kernel.hpp", "dispatch.hpp", "kernels.hip", "gen_sigma.cpp"]
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes_per_cell(d, M, n_e, G, nv, s_op, s_io):
+def n_basis(d, M):
+    return (M + 1) * (M + 2) // 2 if d == 2 else (M + 1) * (M + 2) * (M + 3) // 6
+
+
+def algorithmic_bytes_per_cell(d, M, n_e, nv, s):
     """Bytes one reconstruction must move per cell with precomputed operators.
 
-    operators s_op*[(nb-1)(n_e-1) + (d+1)d^2], int32 gather list 4*G, uint8
-    sector positions (d+1)d and sector mask 1, averages read once nv*s_io,
-    coefficients written once nv*nb*s_io.
+    s [(nb-1)(n_e-1) + (d+1) d^2] operator entries, 4 (n_e-1) bytes of int32
+    stencil indices, d (d+1) bytes of sector positions, and per variable the
+    average read once and the nb coefficients written once.
     """
-    nb = (M + 1) * (M + 2) // 2 if d == 2 else (M + 1) * (M + 2) * (M + 3) // 6
-    return (s_op * ((nb - 1) * (n_e - 1) + (d + 1) * d * d) + 4 * G + (d + 1) * d + 1
-            + nv * s_io + nv * nb * s_io)
+    nb = n_basis(d, M)
+    return s * ((nb - 1) * (n_e - 1) + (d + 1) * d * d) + 4 * (n_e - 1) + d * (d + 1) + nv * s * (1 + nb)
 
 
 def kernel_source_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SRCS:
+        h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(tag):
@@ -63,9 +73,10 @@ def load_traffic(tag):
     return rec.get("bytes_per_launch")
 
 
-def time_path(torch, mesh, q, steps, warmup):
+def time_path(torch, mesh, q, steps, warmup, tune=True):
     out = torch.empty((q.shape[0], mesh.n_basis, mesh.n_cells), dtype=q.dtype, device=q.device)
-    mesh.tune(q, out, repeats=5)            # the library's autotuner picks the kernel variant
+    if tune:
+        mesh.tune(q, out, repeats=5)        # the library's autotuner picks the kernel variant
     for _ in range(warmup):
         mesh.reconstruct(q, out=out)
     torch.cuda.synchronize()
@@ -81,6 +92,37 @@ def time_path(torch, mesh, q, steps, warmup):
     per = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])     # ms
     total = starts[0].elapsed_time(ends[-1])                               # ms
     return dict(total_ms=total, per_ms=per, wall_s=wall, out=out)
+
+
+def measure(torch, C, m, Q, M, factor, steps, warmup, label, d):
+    """Time both precisions on one workload; returns per-precision records."""
+    dev = torch.device("cuda:0")
+    nv = Q.shape[0]
+    t0 = time.perf_counter()
+    lm = C.Mesh(m.vertices, m.cells, M, periodic=m.box, stencil_factor=factor, ops="both")
+    t_pre = time.perf_counter() - t0
+    log(f"{label}: precompute {t_pre:.2f} s, n_e={lm.n_e}, gather={lm.gather_len}, device bytes={lm.device_bytes}")
+    q64 = torch.tensor(Q, dtype=torch.float64, device=dev)
+    res = {"precompute_s": t_pre, "n_e": lm.n_e, "mesh": lm}
+    for tag, q, s in (("f64", q64, 8), ("f32", q64.float(), 4)):
+        r = time_path(torch, lm, q, steps, warmup)
+        got = r["out"][:, 0].cpu().numpy()
+        assert np.array_equal(got, q.cpu().numpy()), "coefficient 0 must copy the input"
+        bpc = algorithmic_bytes_per_cell(d, M, lm.n_e, nv, s)
+        bytes_launch = bpc * m.n_cells
+        ms = r["total_ms"] / steps
+        kern_ms = float(np.mean(r["per_ms"]))
+        achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
+        res[tag] = dict(
+            value=m.n_cells * nv / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms,
+            latency_ms=dict(p50=float(np.percentile(r["per_ms"], 50)), p99=float(np.percentile(r["per_ms"], 99))),
+            roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=achieved / HBM_PEAK_GBS, traffic=None,
+                          algorithmic_bytes_per_cell=bpc, algorithmic_bytes_per_launch=bytes_launch),
+            variant=lm.get_variant(tag, min(nv, 9)))
+        log(f"{label} {tag}: variant {res[tag]['variant']}, {ms:.4f} ms/step, {res[tag]['value']:.3e} cells*vars/s, "
+            f"{achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}% of peak)")
+    return res
 
 
 def cpu_baseline(m, Q, degree, factor, budget_s):
@@ -110,6 +152,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="only the main workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -129,46 +172,42 @@ def main():
 
     import torch
     import paper_1612_09335_amd as C
-    from synthetic import tri_mesh, workload_fields
+    from synthetic import kuhn_tet_mesh, tri_mesh, workload_fields
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
-    dev = torch.device("cuda:0")
     d, M, n, factor = 2, 3, 512, 0.0
     log("generating mesh and fields")
     m = tri_mesh(n, 0.15, SEED)
     Q = workload_fields(m, "mhd2d", SEED)
     nv = Q.shape[0]
-    log("precompute")
-    t0 = time.perf_counter()
-    lm = C.Mesh(m.vertices, m.cells, M, periodic=m.box, stencil_factor=factor, ops="both")
-    t_pre = time.perf_counter() - t0
-    log(f"precompute {t_pre:.2f} s, n_e={lm.n_e}, gather={lm.gather_len}, device bytes={lm.device_bytes}")
-    q64 = torch.tensor(Q, dtype=torch.float64, device=dev)
-    q32 = q64.float()
+    res = measure(torch, C, m, Q, M, factor, args.steps, args.warmup, "tri512 M3", d)
+    for tag in ("f64", "f32"):
+        res[tag]["roofline"]["traffic"] = load_traffic(tag)
 
-    res = {}
-    for tag, q, s in (("f64", q64, 8), ("f32", q32, 4)):
-        log(f"timing {tag}")
-        r = time_path(torch, lm, q, args.steps, args.warmup)
-        got = r["out"][:, 0].cpu().numpy()
-        assert np.array_equal(got, q.cpu().numpy()), "coefficient 0 must copy the input"
-        bpc = algorithmic_bytes_per_cell(d, M, lm.n_e, lm.gather_len, nv, s, s)
-        bytes_launch = bpc * m.n_cells
-        ms = r["total_ms"] / args.steps
-        kern_ms = float(np.mean(r["per_ms"]))
-        achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
-        traffic = load_traffic(tag)
-        res[tag] = dict(
-            value=m.n_cells * nv / (ms * 1e-3), ms_per_step=ms,
-            latency_ms=dict(p50=float(np.percentile(r["per_ms"], 50)), p99=float(np.percentile(r["per_ms"], 99))),
-            roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                          frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                          algorithmic_bytes_per_cell=bpc, algorithmic_bytes_per_launch=bytes_launch))
-        res[tag]["variant"] = lm.get_variant(tag, nv)
-        log(f"{tag}: variant {res[tag]['variant']}, {ms:.4f} ms/step, {res[tag]['value']:.3e} cells*vars/s, {achieved:.0f} GB/s "
-            f"({100 * achieved / HBM_PEAK_GBS:.1f}% of peak)")
+    extras = {}
+    if not args.quick:
+        # small mesh: launch-bound, reported as latency
+        m1 = tri_mesh(64, 0.15, 16120934)
+        Q1 = workload_fields(m1, "euler2d_sod", 16120934)
+        r1 = measure(torch, C, m1, Q1, 2, 1.5, 200, 20, "tri64 M2", 2)
+        extras["tri64_M2_nv4"] = {
+            "workload": "2-D M=2, 8,192 jittered periodic triangles, n_e=9 (stencil factor 1.5), 4 Euler variables",
+            "f64_latency_ms": r1["f64"]["latency_ms"], "f32_latency_ms": r1["f32"]["latency_ms"],
+            "f64_value": r1["f64"]["value"], "f32_value": r1["f32"]["value"], "unit": "cells·vars/s"}
+        del r1
+        # 3-D throughput
+        m3 = kuhn_tet_mesh(64, 0.1, 16120936)
+        Q3 = workload_fields(m3, "euler3d_blast", 16120936)
+        r3 = measure(torch, C, m3, Q3, 3, 0.0, 20, 3, "kuhn64 M3", 3)
+        extras["kuhn64_M3_nv5"] = {
+            "workload": "3-D M=3, 1,572,864 jittered periodic Kuhn tetrahedra, n_e=60, 4 sectors, 5 variables",
+            "precompute_s": r3["precompute_s"]}
+        for tag in ("f64", "f32"):
+            extras["kuhn64_M3_nv5"][tag] = {k: r3[tag][k] for k in ("value", "ms_per_step", "latency_ms", "roofline",
+                                                                   "variant")}
+        del r3
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -184,7 +223,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "CWENO 2-D M=3 (10 basis functions), 524,288 jittered periodic triangles "
                                "(512x512x2), n_e=20, 3 sectors, 9 MHD-shaped variables",
-                   "cells": m.n_cells, "n_vars": nv, "degree": M, "dim": d, "n_e": lm.n_e,
+                   "cells": m.n_cells, "n_vars": nv, "degree": M, "dim": d, "n_e": res["n_e"],
                    "lambda0": 0.95, "eps": 1e-14, "r": 4, "seed": SEED},
         "roofline": r64["roofline"],
         "latency_ms": r64["latency_ms"],
@@ -193,7 +232,8 @@ def main():
                  "latency_ms": res["f32"]["latency_ms"], "roofline": res["f32"]["roofline"],
                  "dtype": "f32"},
         "cpu_baseline": cpu,
-        "precompute_s": t_pre,
+        "precompute_s": res["precompute_s"],
+        "extras": extras,
         "kernel_source_sha": kernel_source_hash(),
     }
     print(json.dumps(line))
