@@ -232,6 +232,46 @@ cweno_status cweno_mesh_get_variant(const cweno_mesh* mesh, cweno_dtype dtype, i
 cweno_status cweno_mesh_tune(cweno_mesh* mesh, int n_vars, cweno_dtype dtype, const void* q, void* coeffs,
                              int repeats, void* hip_stream, double* best_ms);
 
+/*
+ * Batched reconstruction: many meshes in one graph launch (persistent kernels).
+ *
+ * cweno_batch_create  registers `n` device meshes (each holding operators of
+ *                     `dtype`), mesh i to be reconstructed with n_vars[i]
+ *                     variables per run.  The meshes' variable blocks are
+ *                     grouped by (dimension, degree, block size); each group
+ *                     runs as one persistent LDS-halo kernel over a work list
+ *                     of (mesh, block of 256 cells) items.  An autotuner times
+ *                     every halo variant and grid size per group on scratch
+ *                     buffers (zero averages) and keeps the fastest; with a
+ *                     non-NULL tune_cache_path the choices are read from and
+ *                     appended to that text file (one line per group).  The
+ *                     groups are then captured into one HIP graph, one parallel
+ *                     branch per group.  Blocking (it synchronises hip_stream).
+ *                     The meshes must outlive the batch and must not be re-tuned
+ *                     meanwhile.  Errors: CWENO_E_ARG (NULL or host-only mesh,
+ *                     missing precision, a mesh whose block halos do not fit in
+ *                     LDS, sizes beyond 32-bit offsets), CWENO_E_NOMEM,
+ *                     CWENO_E_HIP.
+ * cweno_batch_run     q[i] ([n_vars[i]][n_cells_i]) and coeffs[i]
+ *                     ([n_vars[i]][n_basis_i][n_cells_i]) are device buffers of
+ *                     mesh i, as for cweno_reconstruct.  Asynchronous on
+ *                     hip_stream: one copy of the kernel-parameter table (from
+ *                     pinned host memory) and one graph launch; runs of one batch
+ *                     on different streams are serialised.  It does not allocate.
+ * cweno_batch_info    number of groups, of work items, and the summed tuned time
+ *                     of the group kernels in ms (any pointer may be NULL).
+ * cweno_batch_group   group g: dimension, degree, variable block, entries, work
+ *                     items, chosen variant and grid, tuned time in ms.
+ */
+typedef struct cweno_batch cweno_batch;
+cweno_status cweno_batch_create(int n, cweno_mesh* const* meshes, const int* n_vars, cweno_dtype dtype,
+                                const char* tune_cache_path, void* hip_stream, cweno_batch** out);
+cweno_status cweno_batch_run(cweno_batch* batch, const void* const* q, void* const* coeffs, void* hip_stream);
+cweno_status cweno_batch_info(const cweno_batch* batch, int* n_groups, int64_t* n_items, double* tuned_ms);
+cweno_status cweno_batch_group(const cweno_batch* batch, int g, int* dim, int* degree, int* vb, int* n_entries,
+                               int* n_items, int* variant, int* grid, double* ms);
+cweno_status cweno_batch_destroy(cweno_batch* batch);
+
 const char* cweno_status_string(cweno_status status);
 const char* cweno_last_error(void);
 int cweno_abi_version(void);

@@ -28,7 +28,8 @@ STATUS = {0: "CWENO_OK", -1: "CWENO_E_ARG", -2: "CWENO_E_MESH", -3: "CWENO_E_STE
 SYMBOLS = ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_mesh_tables",
            "cweno_mesh_operators", "cweno_reconstruct", "cweno_status_string", "cweno_last_error",
            "cweno_abi_version", "cweno_num_variants", "cweno_mesh_set_variant", "cweno_mesh_get_variant",
-           "cweno_mesh_tune")
+           "cweno_mesh_tune", "cweno_batch_create", "cweno_batch_run", "cweno_batch_info", "cweno_batch_group",
+           "cweno_batch_destroy")
 
 
 class CwenoError(RuntimeError):
@@ -73,9 +74,18 @@ def _load():
     lib.cweno_status_string.argtypes = [ctypes.c_int]
     lib.cweno_status_string.restype = ctypes.c_char_p
     lib.cweno_last_error.restype = ctypes.c_char_p
+    lib.cweno_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                       ctypes.c_char_p, vp, ctypes.POINTER(vp)]
+    lib.cweno_batch_run.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    lib.cweno_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(i64),
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.cweno_batch_group.argtypes = [vp, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 7 + [
+        ctypes.POINTER(ctypes.c_double)]
+    lib.cweno_batch_destroy.argtypes = [vp]
     for name in ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_mesh_tables",
                  "cweno_mesh_operators", "cweno_reconstruct", "cweno_mesh_set_variant",
-                 "cweno_mesh_get_variant", "cweno_mesh_tune", "cweno_num_variants"):
+                 "cweno_mesh_get_variant", "cweno_mesh_tune", "cweno_num_variants", "cweno_batch_create",
+                 "cweno_batch_run", "cweno_batch_info", "cweno_batch_group", "cweno_batch_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -214,6 +224,65 @@ class Mesh:
 
 def num_variants() -> int:
     return lib.cweno_num_variants()
+
+
+class Batch:
+    """Many meshes reconstructed by one graph launch (cweno_batch_create / cweno_batch_run).
+
+    ``meshes``: device ``Mesh`` objects holding operators of ``dtype``; ``n_vars[i]``
+    variables per run for mesh i.  The meshes are kept alive by the batch.
+    """
+
+    def __init__(self, meshes, n_vars, dtype: str = "f32", tune_cache: str | None = None, stream=None):
+        self.meshes = list(meshes)
+        self.n_vars = [int(v) for v in n_vars]
+        if len(self.n_vars) != len(self.meshes):
+            raise ValueError("one n_vars entry per mesh")
+        self.dtype = dtype
+        n = len(self.meshes)
+        arr = (ctypes.c_void_p * n)(*[m._h.value for m in self.meshes])
+        nv = (ctypes.c_int * n)(*self.n_vars)
+        h = ctypes.c_void_p()
+        _check(lib.cweno_batch_create(n, arr, nv, {"f64": F64, "f32": F32}[dtype],
+                                      None if tune_cache is None else tune_cache.encode(), _stream_ptr(stream),
+                                      ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and lib is not None:
+            lib.cweno_batch_destroy(h)
+            self._h = None
+
+    def run(self, qs, outs, stream=None):
+        """q_i [n_vars_i, n_cells_i] -> outs_i [n_vars_i, n_basis_i, n_cells_i] (torch CUDA tensors)."""
+        import torch
+        tdt = {"f64": torch.float64, "f32": torch.float32}[self.dtype]
+        n = len(self.meshes)
+        if len(qs) != n or len(outs) != n:
+            raise ValueError("one q and one out tensor per mesh")
+        for m, v, q, o in zip(self.meshes, self.n_vars, qs, outs):
+            if (q.dtype != tdt or not q.is_cuda or not q.is_contiguous() or tuple(q.shape) != (v, m.n_cells)
+                    or o.dtype != tdt or not o.is_contiguous() or tuple(o.shape) != (v, m.n_basis, m.n_cells)):
+                raise ValueError("q/out tensors must match each mesh's shape and the batch precision")
+        if stream is None:
+            stream = torch.cuda.current_stream(qs[0].device)
+        qa = (ctypes.c_void_p * n)(*[q.data_ptr() for q in qs])
+        oa = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        _check(lib.cweno_batch_run(self._h, qa, oa, _stream_ptr(stream)))
+        return outs
+
+    def info(self):
+        ng, ni, ms = ctypes.c_int(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib.cweno_batch_info(self._h, ctypes.byref(ng), ctypes.byref(ni), ctypes.byref(ms)))
+        groups = []
+        for g in range(ng.value):
+            vals = [ctypes.c_int() for _ in range(7)]
+            gms = ctypes.c_double()
+            _check(lib.cweno_batch_group(self._h, g, *[ctypes.byref(v) for v in vals], ctypes.byref(gms)))
+            groups.append(dict(zip(("dim", "degree", "vb", "entries", "items", "variant", "grid"),
+                                   [v.value for v in vals]), ms=gms.value))
+        return dict(n_groups=ng.value, n_items=ni.value, tuned_ms=ms.value, groups=groups)
 
 
 def _stream_ptr(stream):

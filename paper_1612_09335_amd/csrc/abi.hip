@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -12,49 +13,42 @@
 #include "cweno.h"
 #include "dispatch.hpp"
 #include "host.hpp"
+#include "mesh.hpp"
+
+namespace cweno_abi {
 
 namespace {
-
 thread_local std::string g_last_error;
+std::mutex g_conf_mu;
+std::vector<int> g_configured;   // devices whose kernels are configured
+}  // namespace
 
 cweno_status fail(cweno_status st, const std::string& msg) {
   g_last_error = msg;
   return st;
 }
 
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
+cweno_status configure_device_kernels() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(CWENO_E_HIP, "no HIP device");
+  std::lock_guard<std::mutex> g(g_conf_mu);
+  for (int d : g_configured)
+    if (d == dev) return CWENO_OK;
+  const hipError_t e = cweno::configure_all();
+  if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("kernel configuration failed: ") + hipGetErrorString(e));
+  g_configured.push_back(dev);
+  return CWENO_OK;
+}
 
-}  // namespace
+const char* last_error() { return g_last_error.c_str(); }
 
-struct cweno_mesh {
-  int d = 2, M = 1, nb = 0, n_e = 0, G = 0;
-  int64_t nc = 0, Np = 0;
-  double lam[5] = {0, 0, 0, 0, 0};
-  double eps = 1e-14;
-  int r = 4;
-  unsigned flags = 0;
-  int ops = CWENO_OPS_F64;
-  int64_t n_dropped = 0;
-  // host copies
-  std::vector<int32_t> nbr, central, sectors;
-  cweno::Operators op;  // FP64 operators (host copy kept only for host-only meshes)
-  // device residency
-  int device = -1;
-  DevBuf pinv64, binv64, sigma64, pinv32, binv32, sigma32, gidx, secpos, mask, halo, hoff, lidx;
-  int maxH = 0;
-  int64_t device_bytes = 0;
-  // kernel variant (index into cweno::kVariants) per [precision][variable block]
-  int variant[2][10];
+}  // namespace cweno_abi
 
-  ~cweno_mesh() {
-    for (DevBuf* b : {&pinv64, &binv64, &sigma64, &pinv32, &binv32, &sigma32, &gidx, &secpos, &mask, &halo,
-                      &hoff, &lidx})
-      if (b->p) (void)hipFree(b->p);
-  }
-};
+using cweno_abi::DevBuf;
+using cweno_abi::fail;
+using cweno_abi::variant_ok;
+using cweno_abi::default_variant;
+using cweno_abi::make_params;
 
 namespace {
 
@@ -79,57 +73,6 @@ cweno_status upload_f32(DevBuf& b, const std::vector<double>& src, hipStream_t s
   std::vector<float> tmp(src.size());
   for (size_t t = 0; t < src.size(); ++t) tmp[t] = (float)src[t];
   return upload(b, tmp.data(), tmp.size() * sizeof(float), s, total);
-}
-
-// Whether variant k can run blocks of vb variables on this mesh: instantiated,
-// and for the halo kernel, the block halos fit in LDS.
-bool variant_ok(const cweno_mesh* m, int vb, int k, bool f32) {
-  const cweno::Variant& V = cweno::kVariants[k];
-  if (!cweno::variant_allowed(m->d, m->M, vb, V, f32)) return false;
-  // the halo kernel stages a block of vb variables through one 32-bit offset range
-  if (V.kind == 1)
-    return m->maxH > 0 && (int64_t)m->maxH * vb * (f32 ? 4 : 8) <= cweno::kMaxLds &&
-           (uint64_t)vb * (uint64_t)m->nc * (f32 ? 4u : 8u) < (uint64_t(1) << 32);
-  return true;
-}
-
-// Default variant: the candidate order below, first one that can run.
-int default_variant(const cweno_mesh* m, int vb, bool f32) {
-  const int order[] = {3, 2, 4, 5, 6, 1, 0};
-  for (int k : order)
-    if (variant_ok(m, vb, k, f32)) return k;
-  return -1;
-}
-
-template <typename T>
-cweno::KParams<T> make_params(const cweno_mesh* m, const void* q, void* coeffs, void* sigma, void* omega, int v0) {
-  const bool f32 = sizeof(T) == 4;
-  cweno::KParams<T> p{};
-  p.q = (const T*)q;
-  p.out = (T*)coeffs;
-  p.sig = (T*)sigma;
-  p.om = (T*)omega;
-  p.pinv = (const T*)(f32 ? m->pinv32.p : m->pinv64.p);
-  p.binv = (const T*)(f32 ? m->binv32.p : m->binv64.p);
-  p.sigma = (const T*)(f32 ? m->sigma32.p : m->sigma64.p);
-  p.gidx = (const int32_t*)m->gidx.p;
-  p.secpos = (const uint8_t*)m->secpos.p;
-  p.mask = (const uint8_t*)m->mask.p;
-  p.halo = (const int32_t*)m->halo.p;
-  p.hoff = (const int32_t*)m->hoff.p;
-  p.lidx = (const uint16_t*)m->lidx.p;
-  p.maxH = m->maxH;
-  p.G = m->G;
-  p.nc = m->nc;
-  p.Np = m->Np;
-  p.NE1 = m->n_e - 1;
-  p.v0 = v0;
-  p.r = m->r;
-  p.sigma0_popt = (m->flags & CWENO_FLAG_SIGMA0_POPT) ? 1 : 0;
-  p.linear_w = (m->flags & CWENO_FLAG_LINEAR_WEIGHTS) ? 1 : 0;
-  for (int t = 0; t < 5; ++t) p.lam[t] = (T)m->lam[t];
-  p.eps = (T)m->eps;
-  return p;
 }
 
 // Launch one variable block [v0, v0+vb) with variant index k.
@@ -175,7 +118,7 @@ extern "C" {
 
 int cweno_abi_version(void) { return CWENO_ABI_VERSION; }
 
-const char* cweno_last_error(void) { return g_last_error.c_str(); }
+const char* cweno_last_error(void) { return cweno_abi::last_error(); }
 
 const char* cweno_status_string(cweno_status st) {
   switch (st) {
@@ -278,6 +221,7 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
   if (!(o.flags & CWENO_FLAG_HOST_ONLY)) {
     hipStream_t s = (hipStream_t)hip_stream;
     if (hipGetDevice(&m->device) != hipSuccess) return fail(CWENO_E_HIP, "no HIP device");
+    if (cweno_status cst = cweno_abi::configure_device_kernels()) return cst;
     const cweno::Operators& op = m->op;
     cweno_status st;
     if (o.ops == CWENO_OPS_F64 || o.ops == CWENO_OPS_BOTH) {

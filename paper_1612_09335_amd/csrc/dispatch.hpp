@@ -40,8 +40,14 @@ inline int pick_vb(int D, int M, int n, bool f32) {
   return 1;
 }
 
-#define CWENO_DECLARE(TN, T, D, M) \
-  hipError_t launch_##TN##_d##D##_m##M(const KParams<T>& p, int vb, int k, hipStream_t s);
+// Per (precision, dimension, degree) unit: one-mesh launch, batched launch
+// (work list over a device table of meshes), and the one-time setting of the
+// dynamic-LDS limit of the unit's halo kernels (outside any stream capture).
+#define CWENO_DECLARE(TN, T, D, M)                                                                    \
+  hipError_t launch_##TN##_d##D##_m##M(const KParams<T>& p, int vb, int k, hipStream_t s);           \
+  hipError_t launch_batch_##TN##_d##D##_m##M(const KParams<T>* table, const BatchItem* items, int n, \
+                                             int grid, size_t lds, int vb, int k, hipStream_t s);    \
+  hipError_t configure_##TN##_d##D##_m##M();
 #define CWENO_DECLARE_T(TN, T) \
   CWENO_DECLARE(TN, T, 2, 1) CWENO_DECLARE(TN, T, 2, 2) CWENO_DECLARE(TN, T, 2, 3) CWENO_DECLARE(TN, T, 2, 4) \
   CWENO_DECLARE(TN, T, 3, 1) CWENO_DECLARE(TN, T, 3, 2) CWENO_DECLARE(TN, T, 3, 3) CWENO_DECLARE(TN, T, 3, 4)
@@ -63,6 +69,37 @@ inline hipError_t launch(int D, int M, const KParams<T>& p, int vb, int k, hipSt
   }
 #undef CWENO_CASE
   return hipErrorInvalidValue;
+}
+
+template <typename T>
+inline hipError_t launch_batch(int D, int M, const KParams<T>* table, const BatchItem* items, int n, int grid,
+                               size_t lds, int vb, int k, hipStream_t s) {
+#define CWENO_CASE(TN, DD, MM) \
+  if (D == DD && M == MM) return launch_batch_##TN##_d##DD##_m##MM(table, items, n, grid, lds, vb, k, s);
+  if constexpr (sizeof(T) == 8) {
+    CWENO_CASE(f64, 2, 1) CWENO_CASE(f64, 2, 2) CWENO_CASE(f64, 2, 3) CWENO_CASE(f64, 2, 4)
+    CWENO_CASE(f64, 3, 1) CWENO_CASE(f64, 3, 2) CWENO_CASE(f64, 3, 3) CWENO_CASE(f64, 3, 4)
+  } else {
+    CWENO_CASE(f32, 2, 1) CWENO_CASE(f32, 2, 2) CWENO_CASE(f32, 2, 3) CWENO_CASE(f32, 2, 4)
+    CWENO_CASE(f32, 3, 1) CWENO_CASE(f32, 3, 2) CWENO_CASE(f32, 3, 3) CWENO_CASE(f32, 3, 4)
+  }
+#undef CWENO_CASE
+  return hipErrorInvalidValue;
+}
+
+// Allow every halo kernel of every unit the full LDS of a workgroup (on the
+// current device).
+inline hipError_t configure_all() {
+  hipError_t (*const fns[])() = {
+      configure_f64_d2_m1, configure_f64_d2_m2, configure_f64_d2_m3, configure_f64_d2_m4,
+      configure_f64_d3_m1, configure_f64_d3_m2, configure_f64_d3_m3, configure_f64_d3_m4,
+      configure_f32_d2_m1, configure_f32_d2_m2, configure_f32_d2_m3, configure_f32_d2_m4,
+      configure_f32_d3_m1, configure_f32_d3_m2, configure_f32_d3_m3, configure_f32_d3_m4};
+  for (auto f : fns) {
+    const hipError_t e = f();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace cweno

@@ -70,17 +70,14 @@ __device__ __forceinline__ void fma_chunk(T (&acc)[NL][VB], const T (&r)[KC][NL]
   }
 }
 
+// One block b of kHaloBlock consecutive cells of the mesh described by p, with
+// lq as the block's LDS halo.  Every thread of the workgroup returns normally.
 template <int D, int M, int VB, int KC, int HU, typename T>
-__global__ __launch_bounds__(kHaloBlock) void reconstruct_halo_kernel(KParams<T> p, CWENO_ARRAY_PARAMS(T)) {
-  CWENO_BIND_ARRAYS(p);
+__device__ __forceinline__ void halo_block(const KParams<T>& p, int64_t b, T* lq) {
   constexpr int NB = nbasis_c(M, D);
   constexpr int NL = NB - 1;
   constexpr int NS = D + 1;
-  extern __shared__ __align__(16) unsigned char halo_raw[];
-  T* const lq = reinterpret_cast<T*>(halo_raw);
-
   const int tid = (int)threadIdx.x;
-  const int64_t b = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i = b * kHaloBlock + tid;
   const bool valid = i < p.nc;
   const int64_t ic = valid ? i : p.nc - 1;
@@ -154,22 +151,67 @@ __global__ __launch_bounds__(kHaloBlock) void reconstruct_halo_kernel(KParams<T>
 
   T lam[NS + 1];
   const T inv_l0 = cell_weights<NS, T>(p, mask, lam);
-  if (!valid) return;
-  T bv[NS][D][D];
-  load_binv<D, T>(p.binv, Np, io, bv);
-  const T* sv = lq + self * VB;
+  if (valid) {
+    T bv[NS][D][D];
+    load_binv<D, T>(p.binv, Np, io, bv);
+    const T* sv = lq + self * VB;
 #pragma unroll
-  for (int v = 0; v < VB; ++v) {
-    const T qi = sv[v];
-    T dqs[NS][D];
+    for (int v = 0; v < VB; ++v) {
+      const T qi = sv[v];
+      T dqs[NS][D];
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
+      for (int s = 0; s < NS; ++s)
 #pragma unroll
-      for (int a = 0; a < D; ++a) dqs[s][a] = lq[sl[s][a] * VB + v] - qi;
-    T po[NL];
+        for (int a = 0; a < D; ++a) dqs[s][a] = lq[sl[s][a] * VB + v] - qi;
+      T po[NL];
 #pragma unroll
-    for (int l = 0; l < NL; ++l) po[l] = acc[l][v];
-    finish_variable<D, M, T>(p, io, v, qi, po, lam, inv_l0, dqs, bv);
+      for (int l = 0; l < NL; ++l) po[l] = acc[l][v];
+      finish_variable<D, M, T>(p, io, v, qi, po, lam, inv_l0, dqs, bv);
+    }
+  }
+}
+
+template <int D, int M, int VB, int KC, int HU, typename T>
+__global__ __launch_bounds__(kHaloBlock) void reconstruct_halo_kernel(KParams<T> p, CWENO_ARRAY_PARAMS(T)) {
+  CWENO_BIND_ARRAYS(p);
+  extern __shared__ __align__(16) unsigned char halo_raw[];
+  halo_block<D, M, VB, KC, HU, T>(p, xcd_block(blockIdx.x, gridDim.x), reinterpret_cast<T*>(halo_raw));
+}
+
+// Work item of the batched kernel: block `block` of the mesh (and variable
+// block) whose parameters are entry `entry` of the batch table.
+struct BatchItem {
+  int32_t entry;
+  int32_t block;
+};
+
+// Batched persistent kernel: every workgroup walks the work list with stride
+// gridDim.x; the parameters of each item's mesh come from a device table (read
+// through the scalar cache).  All meshes of one launch share (D, M, VB) and the
+// LDS size, which covers the largest of their halos.
+// Copy a structure that no kernel writes, word by word through the constant
+// address space (scalar loads).
+template <typename S>
+__device__ __forceinline__ S load_uniform(const S* ptr) {
+  static_assert(sizeof(S) % 4 == 0, "word-sized structure");
+  S out;
+  const __attribute__((address_space(4))) uint32_t* src = (const __attribute__((address_space(4))) uint32_t*)ptr;
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(S) / 4); ++k) dst[k] = src[k];
+  return out;
+}
+
+template <int D, int M, int VB, int KC, int HU, typename T>
+__global__ __launch_bounds__(kHaloBlock) void reconstruct_batch_kernel(const KParams<T>* table,
+                                                                       const BatchItem* items, int n_items) {
+  extern __shared__ __align__(16) unsigned char halo_raw[];
+  T* const lq = reinterpret_cast<T*>(halo_raw);
+  for (int it = (int)blockIdx.x; it < n_items; it += (int)gridDim.x) {
+    const BatchItem w = load_uniform(items + it);
+    const KParams<T> p = load_uniform(table + w.entry);
+    halo_block<D, M, VB, KC, HU, T>(p, w.block, lq);
+    __syncthreads();   // the next item overwrites the halo
   }
 }
 

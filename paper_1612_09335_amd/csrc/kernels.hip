@@ -11,6 +11,10 @@
 #define CWENO_CAT4(a, b, c, d) a##b##c##d
 #define CWENO_NAME(tn, d, m) CWENO_CAT4(launch_, tn, _d##d, _m##m)
 #define CWENO_FN(tn, d, m) CWENO_NAME(tn, d, m)
+#define CWENO_BATCH_NAME(tn, d, m) CWENO_CAT4(launch_batch_, tn, _d##d, _m##m)
+#define CWENO_BATCH_FN(tn, d, m) CWENO_BATCH_NAME(tn, d, m)
+#define CWENO_CONF_NAME(tn, d, m) CWENO_CAT4(configure_, tn, _d##d, _m##m)
+#define CWENO_CONF_FN(tn, d, m) CWENO_CONF_NAME(tn, d, m)
 #define f64 1
 #define f32 2
 #if CWENO_TN == 1
@@ -36,22 +40,70 @@ hipError_t launch_direct(const KParams<real_t>& p, hipStream_t s) {
   }
 }
 
+// The halo kernels' dynamic LDS limit is raised once per device by
+// configure_*() (never during a launch, so that launches can be captured).
 template <int VB, int KC, int HU>
 hipError_t launch_halo(const KParams<real_t>& p, hipStream_t s) {
   if constexpr (vb_allowed(CWENO_D, CWENO_M, VB, sizeof(real_t) == 4)) {
     const int64_t blocks = (p.nc + kHaloBlock - 1) / kHaloBlock;
     const size_t lds = (size_t)p.maxH * VB * sizeof(real_t);
     if (p.maxH <= 0 || lds > (size_t)kMaxLds) return hipErrorInvalidValue;
-    auto fn = reconstruct_halo_kernel<CWENO_D, CWENO_M, VB, KC, HU, real_t>;
-    if (lds > 65536) {
-      hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kHaloBlock), lds, s, p, CWENO_ARRAY_ARGS(p));
+    hipLaunchKernelGGL((reconstruct_halo_kernel<CWENO_D, CWENO_M, VB, KC, HU, real_t>), dim3((unsigned)blocks),
+                       dim3(kHaloBlock), lds, s, p, CWENO_ARRAY_ARGS(p));
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
   }
+}
+
+template <int VB, int KC, int HU>
+hipError_t launch_batch_t(const KParams<real_t>* table, const BatchItem* items, int n, int grid, size_t lds,
+                          hipStream_t s) {
+  if constexpr (vb_allowed(CWENO_D, CWENO_M, VB, sizeof(real_t) == 4)) {
+    if (grid < 1 || n < 1 || lds == 0 || lds > (size_t)kMaxLds) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((reconstruct_batch_kernel<CWENO_D, CWENO_M, VB, KC, HU, real_t>), dim3((unsigned)grid),
+                       dim3(kHaloBlock), lds, s, table, items, n);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int VB, int KC, int HU>
+hipError_t configure_t() {
+  if constexpr (vb_allowed(CWENO_D, CWENO_M, VB, sizeof(real_t) == 4)) {
+    hipError_t e = hipFuncSetAttribute((const void*)reconstruct_halo_kernel<CWENO_D, CWENO_M, VB, KC, HU, real_t>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)reconstruct_batch_kernel<CWENO_D, CWENO_M, VB, KC, HU, real_t>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    return e;
+  } else {
+    return hipSuccess;
+  }
+}
+
+template <int VB>
+hipError_t launch_batch_variant(const KParams<real_t>* table, const BatchItem* items, int n, int grid, size_t lds,
+                                int k, hipStream_t s) {
+  switch (k) {
+    case 2: return launch_batch_t<VB, 1, 4>(table, items, n, grid, lds, s);
+    case 3: return launch_batch_t<VB, 2, 4>(table, items, n, grid, lds, s);
+    case 4: return launch_batch_t<VB, 2, 2>(table, items, n, grid, lds, s);
+    case 5: return launch_batch_t<VB, 2, 8>(table, items, n, grid, lds, s);
+    case 6: return launch_batch_t<VB, 4, 4>(table, items, n, grid, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int VB>
+hipError_t configure_vb() {
+  hipError_t e = configure_t<VB, 1, 4>();
+  if (e == hipSuccess) e = configure_t<VB, 2, 4>();
+  if (e == hipSuccess) e = configure_t<VB, 2, 2>();
+  if (e == hipSuccess) e = configure_t<VB, 2, 8>();
+  if (e == hipSuccess) e = configure_t<VB, 4, 4>();
+  return e;
 }
 
 template <int VB>
@@ -80,6 +132,29 @@ hipError_t CWENO_FN(CWENO_TN, CWENO_D, CWENO_M)(const KParams<real_t>& p, int vb
     case 9: return launch_variant<9>(p, k, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t CWENO_BATCH_FN(CWENO_TN, CWENO_D, CWENO_M)(const KParams<real_t>* table, const BatchItem* items, int n,
+                                                      int grid, size_t lds, int vb, int k, hipStream_t s) {
+  switch (vb) {
+    case 1: return launch_batch_variant<1>(table, items, n, grid, lds, k, s);
+    case 2: return launch_batch_variant<2>(table, items, n, grid, lds, k, s);
+    case 3: return launch_batch_variant<3>(table, items, n, grid, lds, k, s);
+    case 4: return launch_batch_variant<4>(table, items, n, grid, lds, k, s);
+    case 5: return launch_batch_variant<5>(table, items, n, grid, lds, k, s);
+    case 9: return launch_batch_variant<9>(table, items, n, grid, lds, k, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t CWENO_CONF_FN(CWENO_TN, CWENO_D, CWENO_M)() {
+  hipError_t e = configure_vb<1>();
+  if (e == hipSuccess) e = configure_vb<2>();
+  if (e == hipSuccess) e = configure_vb<3>();
+  if (e == hipSuccess) e = configure_vb<4>();
+  if (e == hipSuccess) e = configure_vb<5>();
+  if (e == hipSuccess) e = configure_vb<9>();
+  return e;
 }
 
 }  // namespace cweno

@@ -1,0 +1,110 @@
+// Library-internal view of a registered mesh (shared by the C ABI's
+// translation units; not part of the public interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "cweno.h"
+#include "dispatch.hpp"
+#include "host.hpp"
+
+namespace cweno_abi {
+
+// Records the detail string returned by cweno_last_error (thread-local).
+cweno_status fail(cweno_status st, const std::string& msg);
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Raise the dynamic-LDS limit of every halo kernel once per device (before
+// any launch, so that launches may later be captured into graphs).
+cweno_status configure_device_kernels();
+
+}  // namespace cweno_abi
+
+struct cweno_mesh {
+  int d = 2, M = 1, nb = 0, n_e = 0, G = 0;
+  int64_t nc = 0, Np = 0;
+  double lam[5] = {0, 0, 0, 0, 0};
+  double eps = 1e-14;
+  int r = 4;
+  unsigned flags = 0;
+  int ops = CWENO_OPS_F64;
+  int64_t n_dropped = 0;
+  // host copies
+  std::vector<int32_t> nbr, central, sectors;
+  cweno::Operators op;  // FP64 operators (host copy kept only for host-only meshes)
+  // device residency
+  int device = -1;
+  cweno_abi::DevBuf pinv64, binv64, sigma64, pinv32, binv32, sigma32, gidx, secpos, mask, halo, hoff, lidx;
+  int maxH = 0;
+  int64_t device_bytes = 0;
+  // kernel variant (index into cweno::kVariants) per [precision][variable block]
+  int variant[2][10];
+
+  ~cweno_mesh() {
+    for (cweno_abi::DevBuf* b : {&pinv64, &binv64, &sigma64, &pinv32, &binv32, &sigma32, &gidx, &secpos, &mask, &halo,
+                      &hoff, &lidx})
+      if (b->p) (void)hipFree(b->p);
+  }
+};
+
+namespace cweno_abi {
+
+// Whether variant k can run blocks of vb variables on this mesh: instantiated,
+// and for the halo kernel, the block halos fit in LDS.
+inline bool variant_ok(const cweno_mesh* m, int vb, int k, bool f32) {
+  const cweno::Variant& V = cweno::kVariants[k];
+  if (!cweno::variant_allowed(m->d, m->M, vb, V, f32)) return false;
+  // the halo kernel stages a block of vb variables through one 32-bit offset range
+  if (V.kind == 1)
+    return m->maxH > 0 && (int64_t)m->maxH * vb * (f32 ? 4 : 8) <= cweno::kMaxLds &&
+           (uint64_t)vb * (uint64_t)m->nc * (f32 ? 4u : 8u) < (uint64_t(1) << 32);
+  return true;
+}
+
+// Default variant: the candidate order below, first one that can run.
+inline int default_variant(const cweno_mesh* m, int vb, bool f32) {
+  const int order[] = {3, 2, 4, 5, 6, 1, 0};
+  for (int k : order)
+    if (variant_ok(m, vb, k, f32)) return k;
+  return -1;
+}
+
+template <typename T>
+inline cweno::KParams<T> make_params(const cweno_mesh* m, const void* q, void* coeffs, void* sigma, void* omega, int v0) {
+  const bool f32 = sizeof(T) == 4;
+  cweno::KParams<T> p{};
+  p.q = (const T*)q;
+  p.out = (T*)coeffs;
+  p.sig = (T*)sigma;
+  p.om = (T*)omega;
+  p.pinv = (const T*)(f32 ? m->pinv32.p : m->pinv64.p);
+  p.binv = (const T*)(f32 ? m->binv32.p : m->binv64.p);
+  p.sigma = (const T*)(f32 ? m->sigma32.p : m->sigma64.p);
+  p.gidx = (const int32_t*)m->gidx.p;
+  p.secpos = (const uint8_t*)m->secpos.p;
+  p.mask = (const uint8_t*)m->mask.p;
+  p.halo = (const int32_t*)m->halo.p;
+  p.hoff = (const int32_t*)m->hoff.p;
+  p.lidx = (const uint16_t*)m->lidx.p;
+  p.maxH = m->maxH;
+  p.G = m->G;
+  p.nc = m->nc;
+  p.Np = m->Np;
+  p.NE1 = m->n_e - 1;
+  p.v0 = v0;
+  p.r = m->r;
+  p.sigma0_popt = (m->flags & CWENO_FLAG_SIGMA0_POPT) ? 1 : 0;
+  p.linear_w = (m->flags & CWENO_FLAG_LINEAR_WEIGHTS) ? 1 : 0;
+  for (int t = 0; t < 5; ++t) p.lam[t] = (T)m->lam[t];
+  p.eps = (T)m->eps;
+  return p;
+}
+
+}  // namespace cweno_abi
