@@ -28,7 +28,7 @@ HIP_SOURCES = ["abi.hip", "batch.hip"]
 KERNEL_UNITS = [(tn, d, m) for tn in ("f64", "f32") for d in (2, 3) for m in (1, 2, 3, 4)]
 
 # Integer tables depend on exact floating-point comparisons: no contraction.
-HOST_FLAGS = ["-std=c++17", "-O2", "-fPIC", "-pthread", "-ffp-contract=off", "-Wall", "-Wextra",
+HOST_FLAGS = ["-std=c++17", "-O3", "-fPIC", "-pthread", "-ffp-contract=off", "-Wall", "-Wextra",
               f"-I{INCLUDE}", f"-I{ROCM}/include", "-D__HIP_PLATFORM_AMD__"]
 HIP_FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

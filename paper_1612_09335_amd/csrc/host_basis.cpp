@@ -169,20 +169,50 @@ std::vector<typename Alg::T> dubiner(const Alg& A, int d, int M, const typename 
 
 namespace {
 
-// Allocation-free homogenised Jacobi recurrence for point values.
+// Coefficients of the three-term recurrence below, divided by its leading
+// factor, for n < 8 and alpha < 24 (computed once).
+struct JacobiTable {
+  double c2[8][24], c3[8][24], c4[8][24];
+  JacobiTable() {
+    for (int n = 1; n < 8; ++n)
+      for (int alpha = 0; alpha < 24; ++alpha) {
+        const double a1 = 2.0 * (n + 1) * (n + alpha + 1) * (2.0 * n + alpha);
+        c2[n][alpha] = (2.0 * n + alpha + 1) * alpha * alpha / a1;
+        c3[n][alpha] = (2.0 * n + alpha) * (2.0 * n + alpha + 1) * (2.0 * n + alpha + 2) / a1;
+        c4[n][alpha] = 2.0 * n * (n + alpha) * (2.0 * n + alpha + 2) / a1;
+      }
+  }
+};
+const JacobiTable kJac;
+
+// Allocation-free homogenised Jacobi recurrence for point values
+// (nmax < 8, alpha < 24).
 inline void jacobi_h_pt(double u, double v, int nmax, int alpha, double* H) {
   H[0] = 1.0;
   if (nmax >= 1) H[1] = ((alpha + 2) * u + alpha * v) / 2.0;
   const double v2 = v * v;
-  for (int n = 1; n < nmax; ++n) {
-    double a1 = 2.0 * (n + 1) * (n + alpha + 1) * (2.0 * n + alpha);
-    double a2 = (2.0 * n + alpha + 1) * alpha * alpha;
-    double a3 = (2.0 * n + alpha) * (2.0 * n + alpha + 1) * (2.0 * n + alpha + 2);
-    double a4 = 2.0 * n * (n + alpha) * (2.0 * n + alpha + 2);
-    H[n + 1] = ((a3 * u + a2 * v) * H[n] - a4 * v2 * H[n - 1]) / a1;
-  }
+  for (int n = 1; n < nmax; ++n)
+    H[n + 1] = (kJac.c3[n][alpha] * u + kJac.c2[n][alpha] * v) * H[n] - kJac.c4[n][alpha] * v2 * H[n - 1];
 }
 
+}  // namespace
+
+// Normalisation factors norm_scale(d, {p, q, r}) for p + q + r < 8, computed
+// once (the same expression, so the same bits) instead of one square root
+// per basis function and point.
+namespace {
+struct NormTable {
+  double t2[8][8];
+  double t3[8][8][8];
+  NormTable() {
+    for (int p = 0; p < 8; ++p)
+      for (int q = 0; q < 8; ++q) {
+        t2[p][q] = norm_scale(2, {p, q, 0});
+        for (int r = 0; r < 8; ++r) t3[p][q][r] = norm_scale(3, {p, q, r});
+      }
+  }
+};
+const NormTable kNorm;
 }  // namespace
 
 void basis_eval(int d, int M, const double* xi, double* out) {
@@ -198,7 +228,7 @@ void basis_eval(int d, int M, const double* xi, double* out) {
     for (int n = 0; n <= M; ++n)
       for (int p = n; p >= 0; --p) {
         int q = n - p;
-        out[l++] = norm_scale(2, {p, q, 0}) * F[p] * G[p][q];
+        out[l++] = kNorm.t2[p][q] * F[p] * G[p][q];
       }
     return;
   }
@@ -213,7 +243,7 @@ void basis_eval(int d, int M, const double* xi, double* out) {
     for (int p = n; p >= 0; --p)
       for (int q = n - p; q >= 0; --q) {
         int r = n - p - q;
-        out[l++] = norm_scale(3, {p, q, r}) * F[p] * H[p][q] * K[p][q][r];
+        out[l++] = kNorm.t3[p][q][r] * F[p] * H[p][q] * K[p][q][r];
       }
 }
 

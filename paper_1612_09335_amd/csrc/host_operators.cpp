@@ -97,61 +97,80 @@ double cond2(int n, const double* B) {
 }
 
 // pinv of A (m x n, m >= n, row-major) into P (n x m, row-major) by
-// Householder QR of the column-equilibrated matrix.  Returns false when the
-// matrix is rank deficient.
+// Householder QR of the column-equilibrated matrix: A D^{-1} = Q1 R, so
+// pinv(A) = D^{-1} R^{-1} Q1^T.  Columns are stored contiguously so that every
+// inner loop runs over consecutive memory; Q1 is accumulated backwards from
+// the first n columns of the identity (only columns >= k change under H_k).
+// Returns false when the matrix is rank deficient.
 bool pseudo_inverse(int m, int n, const double* A, double* P) {
-  std::vector<double> R(A, A + (size_t)m * n), scale(n), V((size_t)n * m, 0.0), Qt((size_t)n * m);
+  thread_local std::vector<double> R, V, Q, scale;
+  R.assign((size_t)m * n, 0.0);       // column-major: R[c * m + r]
+  V.assign((size_t)n * m, 0.0);       // reflector k: V[k * m + r], r >= k, unit norm
+  Q.assign((size_t)n * m, 0.0);       // Q1 column-major: Q[c * m + r]
+  scale.assign(n, 0.0);
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < n; ++c) R[(size_t)c * m + r] = A[(size_t)r * n + c];
   for (int c = 0; c < n; ++c) {
+    double* col = &R[(size_t)c * m];
     double s = 0.0;
-    for (int r = 0; r < m; ++r) s += R[(size_t)r * n + c] * R[(size_t)r * n + c];
+    for (int r = 0; r < m; ++r) s += col[r] * col[r];
     s = std::sqrt(s);
     if (!(s > 0.0)) return false;
     scale[c] = s;
-    for (int r = 0; r < m; ++r) R[(size_t)r * n + c] /= s;
+    for (int r = 0; r < m; ++r) col[r] /= s;
   }
   double rmax = 0.0;
   for (int k = 0; k < n; ++k) {
+    double* ck = &R[(size_t)k * m];
     double nrm = 0.0;
-    for (int r = k; r < m; ++r) nrm += R[(size_t)r * n + k] * R[(size_t)r * n + k];
+    for (int r = k; r < m; ++r) nrm += ck[r] * ck[r];
     nrm = std::sqrt(nrm);
-    double* v = &V[(size_t)k * m];
     if (nrm == 0.0) return false;
-    double alpha = R[(size_t)k * n + k] > 0 ? -nrm : nrm;
-    for (int r = k; r < m; ++r) v[r] = R[(size_t)r * n + k];
+    double* v = &V[(size_t)k * m];
+    const double alpha = ck[k] > 0 ? -nrm : nrm;
+    for (int r = k; r < m; ++r) v[r] = ck[r];
     v[k] -= alpha;
     double vn = 0.0;
     for (int r = k; r < m; ++r) vn += v[r] * v[r];
     vn = std::sqrt(vn);
     for (int r = k; r < m; ++r) v[r] /= vn;
     for (int c = k; c < n; ++c) {
+      double* cc = &R[(size_t)c * m];
       double dot = 0.0;
-      for (int r = k; r < m; ++r) dot += v[r] * R[(size_t)r * n + c];
-      for (int r = k; r < m; ++r) R[(size_t)r * n + c] -= 2.0 * v[r] * dot;
+      for (int r = k; r < m; ++r) dot += v[r] * cc[r];
+      const double t = 2.0 * dot;
+      for (int r = k; r < m; ++r) cc[r] -= t * v[r];
     }
-    rmax = std::max(rmax, std::fabs(R[(size_t)k * n + k]));
+    rmax = std::max(rmax, std::fabs(ck[k]));
   }
   for (int k = 0; k < n; ++k)
-    if (!(std::fabs(R[(size_t)k * n + k]) > 1e-12 * rmax)) return false;
-  // Q^T e_j, first n components, for every j: column j of Q1^T
-  std::vector<double> e(m);
-  for (int j = 0; j < m; ++j) {
-    std::fill(e.begin(), e.end(), 0.0);
-    e[j] = 1.0;
-    for (int k = 0; k < n; ++k) {
-      const double* v = &V[(size_t)k * m];
+    if (!(std::fabs(R[(size_t)k * m + k]) > 1e-12 * rmax)) return false;
+  // Q1 = H_0 H_1 ... H_{n-1} [I_n; 0]
+  for (int c = 0; c < n; ++c) Q[(size_t)c * m + c] = 1.0;
+  for (int k = n - 1; k >= 0; --k) {
+    const double* v = &V[(size_t)k * m];
+    for (int c = k; c < n; ++c) {
+      double* qc = &Q[(size_t)c * m];
       double dot = 0.0;
-      for (int r = k; r < m; ++r) dot += v[r] * e[r];
-      for (int r = k; r < m; ++r) e[r] -= 2.0 * v[r] * dot;
+      for (int r = k; r < m; ++r) dot += v[r] * qc[r];
+      const double t = 2.0 * dot;
+      for (int r = k; r < m; ++r) qc[r] -= t * v[r];
     }
-    for (int k = 0; k < n; ++k) Qt[(size_t)k * m + j] = e[k];
   }
-  // back substitution R X = Q1^T, then undo the column scaling
-  for (int j = 0; j < m; ++j)
-    for (int k = n - 1; k >= 0; --k) {
-      double s = Qt[(size_t)k * m + j];
-      for (int c = k + 1; c < n; ++c) s -= R[(size_t)k * n + c] * P[(size_t)c * m + j];
-      P[(size_t)k * m + j] = s / R[(size_t)k * n + k];
+  // R X = Q1^T row by row from the bottom (row k of Q1^T is column k of Q1),
+  // then undo the column scaling
+  for (int k = n - 1; k >= 0; --k) {
+    double* pk = &P[(size_t)k * m];
+    const double* qk = &Q[(size_t)k * m];
+    for (int j = 0; j < m; ++j) pk[j] = qk[j];
+    for (int c = k + 1; c < n; ++c) {
+      const double rkc = R[(size_t)c * m + k];
+      const double* pc = &P[(size_t)c * m];
+      for (int j = 0; j < m; ++j) pk[j] -= rkc * pc[j];
     }
+    const double rkk = R[(size_t)k * m + k];
+    for (int j = 0; j < m; ++j) pk[j] /= rkk;
+  }
   for (int k = 0; k < n; ++k)
     for (int j = 0; j < m; ++j) P[(size_t)k * m + j] /= scale[k];
   return true;

@@ -171,3 +171,19 @@ def workload_mesh(dim: int, n_cells_target: int, seed: int, periodic: bool = Tru
         n = max(3, int(round((n_cells_target / 6.0) ** (1.0 / 3.0))))
         return kuhn_tet_mesh(n, 0.1, seed, periodic)
     raise ValueError("dim must be 2 or 3")
+
+
+def batch_spec(n_meshes: int = 64, lo: float = 1e3, hi: float = 3e5, seed: int = 16120937):
+    """Seeded recipe of a batch of uneven meshes: [(dim, n_cells_target, degree, mesh_seed)].
+
+    Cell counts log-uniform on [lo, hi], dimension uniform in {2, 3}, degree
+    uniform in {2, 3, 4}.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(n_meshes):
+        n = float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        d = int(rng.integers(2, 4))
+        M = int(rng.integers(2, 5))
+        out.append((d, int(round(n)), M, seed + 1 + t))
+    return out
