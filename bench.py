@@ -8,9 +8,11 @@ of the method for every cell and variable), inputs already resident in HBM.
 
 Prints one JSON line.  ``value`` is the FP64 path's cells*vars/s; the FP32
 operator path is reported beside it under "fp32".  Unless --quick is given,
-two more workloads are measured and reported under "extras": the small 2-D
-M=2 mesh (8,192 triangles, 4 Euler variables) as launch latency p50/p99, and
-the 3-D M=3 mesh (1,572,864 Kuhn tetrahedra, 5 variables) as throughput.
+more workloads are measured and reported under "extras": the small 2-D M=2
+mesh (8,192 triangles, 4 Euler variables) as launch latency p50/p99, the 3-D
+M=3 mesh (1,572,864 Kuhn tetrahedra, 5 variables) as throughput, and (unless
+--no-batch) a batch of 64 uneven meshes of mixed dimension and degree as one
+FP32 graph launch against per-mesh FP64 launches.
 """
 from __future__ import annotations
 
@@ -125,6 +127,65 @@ def measure(torch, C, m, Q, M, factor, steps, warmup, label, d):
     return res
 
 
+def time_loop(torch, fn, steps, warmup):
+    """Average ms of fn() over `steps` back-to-back calls on the current stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def measure_batch(torch, C, steps):
+    """64 uneven meshes (seeded recipe): FP32 batch graph vs per-mesh launches."""
+    from synthetic import batch_spec, workload_fields, workload_mesh
+    spec = batch_spec()
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    raw = [(workload_mesh(d, n, sd), M, sd) for d, n, M, sd in spec]
+    Qs = [workload_fields(m, "smooth_jump", sd) for m, M, sd in raw]
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    meshes = [C.Mesh(m.vertices, m.cells, M, periodic=m.box, ops="both") for m, M, sd in raw]
+    t_pre = time.perf_counter() - t0
+    cells = sum(m.n_cells for m, _, _ in raw)
+    cv = sum(m.n_cells * Q.shape[0] for (m, _, _), Q in zip(raw, Qs))
+    log(f"batch: {len(meshes)} meshes, {cells} cells, inputs {t_gen:.1f} s, precompute {t_pre:.1f} s")
+    out = {"workload": f"{len(meshes)} jittered periodic meshes, cell counts log-uniform on [1e3, 3e5] "
+                       f"({cells} cells), d in {{2,3}}, M in {{2,3,4}}, nv = d+2, smooth fields plus a jump",
+           "cells": cells, "cells_vars": cv, "precompute_s": t_pre}
+    for tag, tdt, s in (("f32", torch.float32, 4), ("f64", torch.float64, 8)):
+        qs = [torch.tensor(Q, dtype=tdt, device=dev) for Q in Qs]
+        outs = [torch.empty((Q.shape[0], lm.n_basis, lm.n_cells), dtype=tdt, device=dev)
+                for lm, Q in zip(meshes, Qs)]
+        alg = sum(algorithmic_bytes_per_cell(m.dim, M, lm.n_e, Q.shape[0], s) * m.n_cells
+                  for (m, M, _), lm, Q in zip(raw, meshes, Qs))
+        t0 = time.perf_counter()
+        batch = C.Batch(meshes, [Q.shape[0] for Q in Qs], dtype=tag)
+        t_batch = time.perf_counter() - t0
+        ms_b = time_loop(torch, lambda: batch.run(qs, outs), steps, 3)
+        for lm, q, o in zip(meshes, qs, outs):
+            lm.tune(q, o, repeats=2)
+        ms_m = time_loop(torch, lambda: [lm.reconstruct(q, out=o) for lm, q, o in zip(meshes, qs, outs)], steps, 2)
+        info = batch.info()
+        out[tag] = {
+            "batch_graph_ms": ms_b, "batch_value": cv / (ms_b * 1e-3),
+            "batch_roofline": dict(bound="hbm", achieved=alg / (ms_b * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                                   frac=alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, algorithmic_bytes=alg),
+            "per_mesh_launches_ms": ms_m, "per_mesh_value": cv / (ms_m * 1e-3),
+            "batch_create_s": t_batch, "groups": info["groups"]}
+        log(f"batch {tag}: graph {ms_b:.3f} ms ({cv / (ms_b * 1e-3):.3e} cells*vars/s, "
+            f"{100 * alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS:.1f}% of HBM peak); per-mesh launches {ms_m:.3f} ms")
+        del batch, qs, outs
+    out["f32_batch_vs_f64_per_mesh"] = out["f64"]["per_mesh_launches_ms"] / out["f32"]["batch_graph_ms"]
+    return out
+
+
 def cpu_baseline(m, Q, degree, factor, budget_s):
     """The CPU oracle on a bounded sample of the same workload's cells."""
     from threadpoolctl import threadpool_limits
@@ -153,6 +214,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="only the main workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-mesh batch workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -208,6 +270,12 @@ def main():
             extras["kuhn64_M3_nv5"][tag] = {k: r3[tag][k] for k in ("value", "ms_per_step", "latency_ms", "roofline",
                                                                    "variant")}
         del r3
+        if not args.no_batch:
+            try:
+                extras["batch64_mixed"] = measure_batch(torch, C, 20)
+            except Exception as exc:          # reported, never fatal to the headline line
+                log(f"batch workload failed: {exc!r}")
+                extras["batch64_mixed"] = {"error": repr(exc)}
 
     cpu = None
     if not args.no_cpu_baseline:
