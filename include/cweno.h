@@ -272,6 +272,64 @@ cweno_status cweno_batch_group(const cweno_batch* batch, int g, int* dim, int* d
                                int* n_items, int* variant, int* grid, double* ms);
 cweno_status cweno_batch_destroy(cweno_batch* batch);
 
+/*
+ * Serving: registered meshes, HBM residency under a budget, requests scheduled
+ * as they arrive.
+ *
+ * cweno_server_create    an HBM arena of hbm_budget_bytes is allocated now (the
+ *                        serving loop never allocates or frees device memory);
+ *                        operators are kept in precision op_dtype; at most
+ *                        max_inflight requests run at once, spread over
+ *                        n_streams compute streams.  A scheduler thread and a
+ *                        completion thread start here.
+ * cweno_server_register  host precompute of a mesh (arguments as for
+ *                        cweno_mesh_create; opt->ops and HOST_ONLY are set by
+ *                        the server) and one pinned host image of its whole
+ *                        device layout.  *mesh_id receives its id.
+ *                        CWENO_E_BUDGET if the image alone exceeds the budget.
+ * cweno_server_mesh_info cells, basis size, image bytes, currently resident.
+ * cweno_server_submit    non-blocking: queues a reconstruction of mesh mesh_id
+ *                        (q, coeffs: device buffers as for cweno_reconstruct,
+ *                        in the server's precision, valid until the request is
+ *                        done; the server's streams do not wait for the
+ *                        caller's, so q must already hold its values) and
+ *                        returns a ticket.  Requests are admitted in
+ *                        submission order; a mesh that is not resident is
+ *                        uploaded into the arena, evicting the least recently
+ *                        used meshes that no running request uses.
+ * cweno_server_poll      *done = 1 once the request has finished (or was
+ *                        cancelled: CWENO_E_CANCELLED; or failed: CWENO_E_HIP).
+ * cweno_server_wait      blocks until the request finishes or timeout_s passes
+ *                        (timeout_s < 0: no limit; CWENO_E_BUSY on timeout).
+ * cweno_server_cancel    removes a request that has not started
+ *                        (CWENO_E_BUSY if it is running or finished).
+ * cweno_server_stats     latency quantiles in seconds (completion seen by the
+ *                        host minus submission), completed requests, evictions,
+ *                        uploads and uploaded bytes since creation or the last
+ *                        cweno_server_reset_stats.  Any pointer may be NULL.
+ * cweno_server_pause     paused != 0 holds admission (submitted requests stay
+ *                        queued and can be cancelled); 0 resumes it.
+ * cweno_server_destroy   cancels queued requests, waits for running ones.
+ */
+typedef struct cweno_server cweno_server;
+cweno_status cweno_server_create(int64_t hbm_budget_bytes, cweno_dtype op_dtype, int max_inflight, int n_streams,
+                                 cweno_server** out);
+cweno_status cweno_server_register(cweno_server* server, int dim, int64_t n_vertices, const double* vertices,
+                                   int64_t n_cells, const int32_t* cells, int degree, const cweno_options* opt,
+                                   int64_t* mesh_id);
+cweno_status cweno_server_mesh_info(cweno_server* server, int64_t mesh_id, int64_t* n_cells, int* n_basis,
+                                    int64_t* image_bytes, int* resident);
+cweno_status cweno_server_submit(cweno_server* server, int64_t mesh_id, int n_vars, cweno_dtype dtype,
+                                 const void* q, void* coeffs, int64_t* ticket);
+cweno_status cweno_server_poll(cweno_server* server, int64_t ticket, int* done);
+cweno_status cweno_server_wait(cweno_server* server, int64_t ticket, double timeout_s);
+cweno_status cweno_server_cancel(cweno_server* server, int64_t ticket);
+cweno_status cweno_server_stats(cweno_server* server, double* p50_s, double* p99_s, double* p999_s,
+                                int64_t* completed, int64_t* evictions, int64_t* uploads, int64_t* upload_bytes);
+cweno_status cweno_server_reset_stats(cweno_server* server);
+cweno_status cweno_server_pause(cweno_server* server, int paused);
+cweno_status cweno_server_destroy(cweno_server* server);
+
 const char* cweno_status_string(cweno_status status);
 const char* cweno_last_error(void);
 int cweno_abi_version(void);

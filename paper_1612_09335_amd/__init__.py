@@ -29,7 +29,9 @@ SYMBOLS = ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_
            "cweno_mesh_operators", "cweno_reconstruct", "cweno_status_string", "cweno_last_error",
            "cweno_abi_version", "cweno_num_variants", "cweno_mesh_set_variant", "cweno_mesh_get_variant",
            "cweno_mesh_tune", "cweno_batch_create", "cweno_batch_run", "cweno_batch_info", "cweno_batch_group",
-           "cweno_batch_destroy")
+           "cweno_batch_destroy", "cweno_server_create", "cweno_server_register", "cweno_server_mesh_info",
+           "cweno_server_submit", "cweno_server_poll", "cweno_server_wait", "cweno_server_cancel",
+           "cweno_server_stats", "cweno_server_reset_stats", "cweno_server_pause", "cweno_server_destroy")
 
 
 class CwenoError(RuntimeError):
@@ -82,10 +84,28 @@ def _load():
     lib.cweno_batch_group.argtypes = [vp, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 7 + [
         ctypes.POINTER(ctypes.c_double)]
     lib.cweno_batch_destroy.argtypes = [vp]
+    i64p = ctypes.POINTER(i64)
+    lib.cweno_server_create.argtypes = [i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
+    lib.cweno_server_register.argtypes = [vp, ctypes.c_int, i64, vp, i64, vp, ctypes.c_int, ctypes.POINTER(_Options),
+                                          i64p]
+    lib.cweno_server_mesh_info.argtypes = [vp, i64, i64p, ctypes.POINTER(ctypes.c_int), i64p,
+                                           ctypes.POINTER(ctypes.c_int)]
+    lib.cweno_server_submit.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, vp, vp, i64p]
+    lib.cweno_server_poll.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_int)]
+    lib.cweno_server_wait.argtypes = [vp, i64, ctypes.c_double]
+    lib.cweno_server_cancel.argtypes = [vp, i64]
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.cweno_server_stats.argtypes = [vp, dp, dp, dp, i64p, i64p, i64p, i64p]
+    lib.cweno_server_reset_stats.argtypes = [vp]
+    lib.cweno_server_pause.argtypes = [vp, ctypes.c_int]
+    lib.cweno_server_destroy.argtypes = [vp]
     for name in ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_mesh_tables",
                  "cweno_mesh_operators", "cweno_reconstruct", "cweno_mesh_set_variant",
                  "cweno_mesh_get_variant", "cweno_mesh_tune", "cweno_num_variants", "cweno_batch_create",
-                 "cweno_batch_run", "cweno_batch_info", "cweno_batch_group", "cweno_batch_destroy"):
+                 "cweno_batch_run", "cweno_batch_info", "cweno_batch_group", "cweno_batch_destroy",
+                 "cweno_server_create", "cweno_server_register", "cweno_server_mesh_info", "cweno_server_submit",
+                 "cweno_server_poll", "cweno_server_wait", "cweno_server_cancel", "cweno_server_stats",
+                 "cweno_server_reset_stats", "cweno_server_pause", "cweno_server_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -283,6 +303,84 @@ class Batch:
             groups.append(dict(zip(("dim", "degree", "vb", "entries", "items", "variant", "grid"),
                                    [v.value for v in vals]), ms=gms.value))
         return dict(n_groups=ng.value, n_items=ni.value, tuned_ms=ms.value, groups=groups)
+
+
+class Server:
+    """Serving loop (cweno_server_*): registered meshes, HBM residency under a
+    budget with least-recently-used eviction, requests scheduled as they arrive."""
+
+    def __init__(self, hbm_budget_bytes: int, dtype: str = "f32", max_inflight: int = 8, n_streams: int = 4):
+        self.dtype = dtype
+        h = ctypes.c_void_p()
+        _check(lib.cweno_server_create(int(hbm_budget_bytes), {"f64": F64, "f32": F32}[dtype], int(max_inflight),
+                                       int(n_streams), ctypes.byref(h)))
+        self._h = h
+        self._meshes = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and lib is not None:
+            lib.cweno_server_destroy(h)
+            self._h = None
+
+    def register(self, vertices, cells, degree: int, periodic=(0.0, 0.0, 0.0), stencil_factor: float = 0.0,
+                 lambda0: float = 0.0, eps: float = 0.0, r: int = 0, sector_rule: str = "cone") -> int:
+        V = np.ascontiguousarray(vertices, dtype=np.float64)
+        C = np.ascontiguousarray(cells, dtype=np.int32)
+        o = _Options()
+        for a, L in enumerate(tuple(periodic)[:3]):
+            o.periodic[a] = float(L)
+        o.stencil_factor, o.lambda0, o.eps, o.r = float(stencil_factor), float(lambda0), float(eps), int(r)
+        o.sector_rule = SECTOR_RULES[sector_rule]
+        mid = ctypes.c_int64()
+        _check(lib.cweno_server_register(self._h, V.shape[1], V.shape[0], V.ctypes.data, C.shape[0], C.ctypes.data,
+                                         int(degree), ctypes.byref(o), ctypes.byref(mid)))
+        self._meshes[mid.value] = self.mesh_info(mid.value)
+        return mid.value
+
+    def mesh_info(self, mesh_id: int):
+        n, nb, ib, res = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int64(), ctypes.c_int()
+        _check(lib.cweno_server_mesh_info(self._h, int(mesh_id), ctypes.byref(n), ctypes.byref(nb), ctypes.byref(ib),
+                                          ctypes.byref(res)))
+        return dict(n_cells=n.value, n_basis=nb.value, image_bytes=ib.value, resident=bool(res.value))
+
+    def submit(self, mesh_id: int, q, out) -> int:
+        """Queue a reconstruction of q [n_vars, n_cells] into out [n_vars, n_basis, n_cells] (torch CUDA)."""
+        info = self._meshes[mesh_id]
+        nv = q.shape[0]
+        if (not q.is_cuda or not q.is_contiguous() or not out.is_contiguous() or q.dim() != 2
+                or q.shape[1] != info["n_cells"] or tuple(out.shape) != (nv, info["n_basis"], info["n_cells"])
+                or out.dtype != q.dtype):
+            raise ValueError("q/out must be contiguous CUDA tensors matching the mesh")
+        t = ctypes.c_int64()
+        dt = F32 if str(q.dtype) == "torch.float32" else F64
+        _check(lib.cweno_server_submit(self._h, int(mesh_id), nv, dt, q.data_ptr(), out.data_ptr(), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        done = ctypes.c_int()
+        _check(lib.cweno_server_poll(self._h, int(ticket), ctypes.byref(done)))
+        return bool(done.value)
+
+    def wait(self, ticket: int, timeout_s: float = -1.0):
+        _check(lib.cweno_server_wait(self._h, int(ticket), float(timeout_s)))
+
+    def cancel(self, ticket: int):
+        _check(lib.cweno_server_cancel(self._h, int(ticket)))
+
+    def pause(self, paused: bool = True):
+        _check(lib.cweno_server_pause(self._h, 1 if paused else 0))
+
+    def stats(self):
+        p50, p99, p999 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        c, e, u, ub = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.cweno_server_stats(self._h, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(p999),
+                                      ctypes.byref(c), ctypes.byref(e), ctypes.byref(u), ctypes.byref(ub)))
+        return dict(p50_s=p50.value, p99_s=p99.value, p999_s=p999.value, completed=c.value, evictions=e.value,
+                    uploads=u.value, upload_bytes=ub.value)
+
+    def reset_stats(self):
+        _check(lib.cweno_server_reset_stats(self._h))
 
 
 def _stream_ptr(stream):

@@ -49,6 +49,7 @@ using cweno_abi::fail;
 using cweno_abi::variant_ok;
 using cweno_abi::default_variant;
 using cweno_abi::make_params;
+using cweno_abi::launch_block;
 
 namespace {
 
@@ -73,14 +74,6 @@ cweno_status upload_f32(DevBuf& b, const std::vector<double>& src, hipStream_t s
   std::vector<float> tmp(src.size());
   for (size_t t = 0; t < src.size(); ++t) tmp[t] = (float)src[t];
   return upload(b, tmp.data(), tmp.size() * sizeof(float), s, total);
-}
-
-// Launch one variable block [v0, v0+vb) with variant index k.
-hipError_t launch_block(const cweno_mesh* m, bool f32, const void* q, void* coeffs, void* sigma, void* omega,
-                        int v0, int vb, int k, hipStream_t s) {
-  if (f32)
-    return cweno::launch<float>(m->d, m->M, make_params<float>(m, q, coeffs, sigma, omega, v0), vb, k, s);
-  return cweno::launch<double>(m->d, m->M, make_params<double>(m, q, coeffs, sigma, omega, v0), vb, k, s);
 }
 
 // Whether [a, a + na) and [b, b + nb) share a byte (empty ranges never do).

@@ -44,12 +44,14 @@ struct cweno_mesh {
   cweno_abi::DevBuf pinv64, binv64, sigma64, pinv32, binv32, sigma32, gidx, secpos, mask, halo, hoff, lidx;
   int maxH = 0;
   int64_t device_bytes = 0;
+  bool owns_device = true;   // false: the device buffers point into memory owned elsewhere (a server arena)
   // kernel variant (index into cweno::kVariants) per [precision][variable block]
   int variant[2][10];
 
   ~cweno_mesh() {
+    if (!owns_device) return;
     for (cweno_abi::DevBuf* b : {&pinv64, &binv64, &sigma64, &pinv32, &binv32, &sigma32, &gidx, &secpos, &mask, &halo,
-                      &hoff, &lidx})
+                                 &hoff, &lidx})
       if (b->p) (void)hipFree(b->p);
   }
 };
@@ -105,6 +107,14 @@ inline cweno::KParams<T> make_params(const cweno_mesh* m, const void* q, void* c
   for (int t = 0; t < 5; ++t) p.lam[t] = (T)m->lam[t];
   p.eps = (T)m->eps;
   return p;
+}
+
+// Launch one variable block [v0, v0+vb) with variant index k.
+inline hipError_t launch_block(const cweno_mesh* m, bool f32, const void* q, void* coeffs, void* sigma, void* omega,
+                        int v0, int vb, int k, hipStream_t s) {
+  if (f32)
+    return cweno::launch<float>(m->d, m->M, make_params<float>(m, q, coeffs, sigma, omega, v0), vb, k, s);
+  return cweno::launch<double>(m->d, m->M, make_params<double>(m, q, coeffs, sigma, omega, v0), vb, k, s);
 }
 
 }  // namespace cweno_abi
