@@ -12,7 +12,10 @@ more workloads are measured and reported under "extras": the small 2-D M=2
 mesh (8,192 triangles, 4 Euler variables) as launch latency p50/p99, the 3-D
 M=3 mesh (1,572,864 Kuhn tetrahedra, 5 variables) as throughput, and (unless
 --no-batch) a batch of 64 uneven meshes of mixed dimension and degree as one
-FP32 graph launch against per-mesh FP64 launches.
+FP32 graph launch against per-mesh FP64 launches, and (unless
+--serve-seconds 0) the serving loop: 200 registered meshes, HBM budget half
+their footprint, Poisson request arrivals; latency p50/p99/p99.9 against a
+serial FP64 server.
 """
 from __future__ import annotations
 
@@ -186,6 +189,73 @@ def measure_batch(torch, C, steps):
     return out
 
 
+def serve_run(torch, srv, ids, qs, outs, cv, arrivals, picks):
+    """Submit requests at their scheduled times; returns latency and throughput figures."""
+    t0 = time.perf_counter() + 0.05
+    tickets, lag = [], 0.0
+    for a, k in zip(arrivals, picks):
+        ts = t0 + a
+        now = time.perf_counter()
+        while now < ts:
+            now = time.perf_counter()
+        lag = max(lag, now - ts)
+        tickets.append(srv.submit(ids[k], qs[k], outs[k]))
+    for t in tickets:
+        srv.wait(t, 600.0)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    served = sum(cv[k] for k in picks)
+    return dict(requests=len(tickets), p50_ms=1e3 * st["p50_s"], p99_ms=1e3 * st["p99_s"],
+                p999_ms=1e3 * st["p999_s"], evictions=st["evictions"], uploads=st["uploads"],
+                upload_gb=st["upload_bytes"] / 1e9, wall_s=wall, value=served / wall,
+                max_submit_lag_ms=1e3 * lag)
+
+
+def measure_serving(torch, C, seconds, rate=2000.0, n_meshes=200, lo=1e3, hi=2e4, nv=5):
+    """Registered meshes served under half their footprint in HBM, Poisson arrivals."""
+    from synthetic import batch_spec, workload_mesh
+    spec = batch_spec(n_meshes, lo, hi, seed=16120938)
+    t0 = time.perf_counter()
+    raw = [(workload_mesh(d, n, sd), M) for d, n, M, sd in spec]
+    hosts = [C.Mesh(m.vertices, m.cells, M, periodic=m.box, host_only=True) for m, M in raw]
+    t_pre = time.perf_counter() - t0
+    cells = sum(m.n_cells for m, _ in raw)
+    cv = [m.n_cells * nv for m, _ in raw]
+    rng = np.random.default_rng(16120939)
+    n_req = int(seconds * rate)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    picks = [int(k) for k in rng.integers(0, n_meshes, size=n_req)]
+    out = {"workload": f"{n_meshes} registered meshes, cell counts log-uniform on [{lo:.0e}, {hi:.0e}] ({cells} "
+                       f"cells), d in {{2,3}}, M in {{2,3,4}}, {nv} variables; Poisson arrivals at {rate:.0f}/s, "
+                       f"uniform mesh choice; HBM budget half the registered footprint",
+           "cells": cells, "precompute_s": t_pre}
+    log(f"serving: {n_meshes} meshes, {cells} cells, precompute {t_pre:.1f} s")
+    for tag, tdt, inflight, streams, secs in (("f32", torch.float32, 16, 16, seconds),
+                                              ("f64_serial", torch.float64, 1, 1, min(seconds, 2.0))):
+        dt = "f32" if tag == "f32" else "f64"
+        probe = C.Server(64 << 30, dtype=dt)
+        foot = sum(probe.mesh_info(probe.register_mesh(h))["image_bytes"] for h in hosts)
+        del probe
+        budget = foot // 2
+        srv = C.Server(budget, dtype=dt, max_inflight=inflight, n_streams=streams)
+        ids = [srv.register_mesh(h) for h in hosts]
+        qs = [torch.tensor(rng.normal(size=(nv, m.n_cells)), dtype=tdt, device="cuda:0") for m, _ in raw]
+        outs = [torch.empty((nv, h.n_basis, h.n_cells), dtype=tdt, device="cuda:0") for h in hosts]
+        torch.cuda.synchronize()
+        # warm-up: a pass over a few meshes, then clean statistics
+        for k in range(min(8, n_meshes)):
+            srv.wait(srv.submit(ids[k], qs[k], outs[k]), 60.0)
+        srv.reset_stats()
+        n = int(secs * rate)
+        r = serve_run(torch, srv, ids, qs, outs, cv, arrivals[:n], picks[:n])
+        r.update(footprint_gb=foot / 1e9, budget_gb=budget / 1e9, max_inflight=inflight, streams=streams)
+        out[tag] = r
+        log(f"serving {tag}: {r['requests']} requests, p50 {r['p50_ms']:.3f} ms, p99 {r['p99_ms']:.3f} ms, "
+            f"p99.9 {r['p999_ms']:.3f} ms, {r['value']:.3e} cells*vars/s, evictions {r['evictions']}")
+        del srv, qs, outs
+    return out
+
+
 def cpu_baseline(m, Q, degree, factor, budget_s):
     """The CPU oracle on a bounded sample of the same workload's cells."""
     from threadpoolctl import threadpool_limits
@@ -215,6 +285,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="only the main workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-mesh batch workload")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the serving run (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -276,6 +348,12 @@ def main():
             except Exception as exc:          # reported, never fatal to the headline line
                 log(f"batch workload failed: {exc!r}")
                 extras["batch64_mixed"] = {"error": repr(exc)}
+        if args.serve_seconds > 0:
+            try:
+                extras["serving"] = measure_serving(torch, C, args.serve_seconds)
+            except Exception as exc:          # reported, never fatal to the headline line
+                log(f"serving workload failed: {exc!r}")
+                extras["serving"] = {"error": repr(exc)}
 
     cpu = None
     if not args.no_cpu_baseline:

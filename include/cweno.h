@@ -287,6 +287,9 @@ cweno_status cweno_batch_destroy(cweno_batch* batch);
  *                        the server) and one pinned host image of its whole
  *                        device layout.  *mesh_id receives its id.
  *                        CWENO_E_BUDGET if the image alone exceeds the budget.
+ * cweno_server_register_mesh  the same from a mesh built with CWENO_FLAG_HOST_ONLY
+ *                        (its precompute is reused; the caller keeps ownership
+ *                        of host_mesh, which may be destroyed afterwards).
  * cweno_server_mesh_info cells, basis size, image bytes, currently resident.
  * cweno_server_submit    non-blocking: queues a reconstruction of mesh mesh_id
  *                        (q, coeffs: device buffers as for cweno_reconstruct,
@@ -317,6 +320,7 @@ cweno_status cweno_server_create(int64_t hbm_budget_bytes, cweno_dtype op_dtype,
 cweno_status cweno_server_register(cweno_server* server, int dim, int64_t n_vertices, const double* vertices,
                                    int64_t n_cells, const int32_t* cells, int degree, const cweno_options* opt,
                                    int64_t* mesh_id);
+cweno_status cweno_server_register_mesh(cweno_server* server, const cweno_mesh* host_mesh, int64_t* mesh_id);
 cweno_status cweno_server_mesh_info(cweno_server* server, int64_t mesh_id, int64_t* n_cells, int* n_basis,
                                     int64_t* image_bytes, int* resident);
 cweno_status cweno_server_submit(cweno_server* server, int64_t mesh_id, int n_vars, cweno_dtype dtype,

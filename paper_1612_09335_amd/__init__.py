@@ -29,8 +29,8 @@ SYMBOLS = ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_
            "cweno_mesh_operators", "cweno_reconstruct", "cweno_status_string", "cweno_last_error",
            "cweno_abi_version", "cweno_num_variants", "cweno_mesh_set_variant", "cweno_mesh_get_variant",
            "cweno_mesh_tune", "cweno_batch_create", "cweno_batch_run", "cweno_batch_info", "cweno_batch_group",
-           "cweno_batch_destroy", "cweno_server_create", "cweno_server_register", "cweno_server_mesh_info",
-           "cweno_server_submit", "cweno_server_poll", "cweno_server_wait", "cweno_server_cancel",
+           "cweno_batch_destroy", "cweno_server_create", "cweno_server_register", "cweno_server_register_mesh",
+           "cweno_server_mesh_info", "cweno_server_submit", "cweno_server_poll", "cweno_server_wait", "cweno_server_cancel",
            "cweno_server_stats", "cweno_server_reset_stats", "cweno_server_pause", "cweno_server_destroy")
 
 
@@ -88,6 +88,7 @@ def _load():
     lib.cweno_server_create.argtypes = [i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
     lib.cweno_server_register.argtypes = [vp, ctypes.c_int, i64, vp, i64, vp, ctypes.c_int, ctypes.POINTER(_Options),
                                           i64p]
+    lib.cweno_server_register_mesh.argtypes = [vp, vp, i64p]
     lib.cweno_server_mesh_info.argtypes = [vp, i64, i64p, ctypes.POINTER(ctypes.c_int), i64p,
                                            ctypes.POINTER(ctypes.c_int)]
     lib.cweno_server_submit.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, vp, vp, i64p]
@@ -103,7 +104,8 @@ def _load():
                  "cweno_mesh_operators", "cweno_reconstruct", "cweno_mesh_set_variant",
                  "cweno_mesh_get_variant", "cweno_mesh_tune", "cweno_num_variants", "cweno_batch_create",
                  "cweno_batch_run", "cweno_batch_info", "cweno_batch_group", "cweno_batch_destroy",
-                 "cweno_server_create", "cweno_server_register", "cweno_server_mesh_info", "cweno_server_submit",
+                 "cweno_server_create", "cweno_server_register", "cweno_server_register_mesh",
+                 "cweno_server_mesh_info", "cweno_server_submit",
                  "cweno_server_poll", "cweno_server_wait", "cweno_server_cancel", "cweno_server_stats",
                  "cweno_server_reset_stats", "cweno_server_pause", "cweno_server_destroy"):
         getattr(lib, name).restype = ctypes.c_int
@@ -335,6 +337,13 @@ class Server:
         mid = ctypes.c_int64()
         _check(lib.cweno_server_register(self._h, V.shape[1], V.shape[0], V.ctypes.data, C.shape[0], C.ctypes.data,
                                          int(degree), ctypes.byref(o), ctypes.byref(mid)))
+        self._meshes[mid.value] = self.mesh_info(mid.value)
+        return mid.value
+
+    def register_mesh(self, mesh) -> int:
+        """Register a ``Mesh`` built with host_only=True, reusing its precompute."""
+        mid = ctypes.c_int64()
+        _check(lib.cweno_server_register_mesh(self._h, mesh._h, ctypes.byref(mid)))
         self._meshes[mid.value] = self.mesh_info(mid.value)
         return mid.value
 

@@ -10,8 +10,8 @@
 //   used mesh with no request in flight is evicted when a placement fails.
 //   The serving loop never allocates or frees device memory.
 // * A scheduler thread admits queued requests in arrival order, up to
-//   max_inflight at a time: it makes the mesh resident (upload on a copy
-//   stream, recorded in an event), pins it, and launches the reconstruction
+//   max_inflight at a time: it makes the mesh resident (upload on one of two
+//   copy streams, recorded in an event), pins it, and launches the reconstruction
 //   on one of several compute streams (round robin) after the upload event,
 //   so that a request waiting for its upload does not hold back the others.
 // * A completion thread polls the in-flight requests' events, records each
@@ -40,6 +40,7 @@ using cweno_abi::fail;
 namespace {
 
 constexpr size_t kGranule = 256;
+constexpr int kCopyStreams = 2;   // uploads alternate between two copy streams
 
 size_t round_up(size_t x) { return (x + kGranule - 1) / kGranule * kGranule; }
 
@@ -124,7 +125,8 @@ struct cweno_server {
   size_t budget = 0;
   void* arena_base = nullptr;
   Arena arena;
-  hipStream_t copy = nullptr;
+  std::vector<hipStream_t> copy;     // uploads, round robin (several DMA engines)
+  int next_copy = 0;
   std::vector<hipStream_t> comp;
   int next_stream = 0;
   std::vector<std::unique_ptr<SMesh>> meshes;
@@ -199,8 +201,10 @@ bool cweno_server::make_resident(SMesh& sm) {
   sm.resident = true;
   char* base = static_cast<char*>(arena_base) + off;
   point_buffers(sm, base);
-  hipError_t e = hipMemcpyAsync(base, sm.image, sm.lay.total, hipMemcpyHostToDevice, copy);
-  if (e == hipSuccess) e = hipEventRecord(sm.ready, copy);
+  hipStream_t cs = copy[next_copy];
+  next_copy = (next_copy + 1) % (int)copy.size();
+  hipError_t e = hipMemcpyAsync(base, sm.image, sm.lay.total, hipMemcpyHostToDevice, cs);
+  if (e == hipSuccess) e = hipEventRecord(sm.ready, cs);
   if (e != hipSuccess) async_error = std::string("upload failed: ") + hipGetErrorString(e);
   ++uploads;
   upload_bytes += (int64_t)sm.lay.total;
@@ -320,10 +324,11 @@ cweno_server::~cweno_server() {
       (void)hipStreamSynchronize(s);
       (void)hipStreamDestroy(s);
     }
-  if (copy) {
-    (void)hipStreamSynchronize(copy);
-    (void)hipStreamDestroy(copy);
-  }
+  for (hipStream_t s : copy)
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
   for (hipEvent_t e : event_pool)
     if (e) (void)hipEventDestroy(e);
   for (auto& sm : meshes) {
@@ -406,8 +411,10 @@ cweno_status cweno_server_create(int64_t hbm_budget_bytes, cweno_dtype op_dtype,
   if (hipMalloc(&s->arena_base, s->budget) != hipSuccess)
     return fail(CWENO_E_NOMEM, "cannot allocate an HBM arena of the requested budget");
   s->arena.reset(s->budget);
-  if (hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess)
-    return fail(CWENO_E_HIP, "stream creation failed");
+  s->copy.assign(kCopyStreams, nullptr);
+  for (hipStream_t& x : s->copy)
+    if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess)
+      return fail(CWENO_E_HIP, "stream creation failed");
   s->comp.assign(n_streams, nullptr);
   for (hipStream_t& x : s->comp)
     if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess)
@@ -422,17 +429,10 @@ cweno_status cweno_server_create(int64_t hbm_budget_bytes, cweno_dtype op_dtype,
   return CWENO_OK;
 }
 
-cweno_status cweno_server_register(cweno_server* s, int dim, int64_t n_vertices, const double* vertices,
-                                   int64_t n_cells, const int32_t* cells, int degree, const cweno_options* opt,
-                                   int64_t* mesh_id) {
-  if (!s || !mesh_id) return fail(CWENO_E_ARG, "server and mesh_id must not be NULL");
-  cweno_options o{};
-  if (opt) o = *opt;
-  o.flags |= CWENO_FLAG_HOST_ONLY;
-  o.ops = s->f32 ? CWENO_OPS_F32 : CWENO_OPS_F64;
-  cweno_mesh* raw = nullptr;
-  if (cweno_status st = cweno_mesh_create(dim, n_vertices, vertices, n_cells, cells, degree, &o, nullptr, &raw))
-    return st;
+namespace {
+
+// Take over a host-only mesh (its FP64 operators present) as a server mesh.
+cweno_status adopt(cweno_server* s, cweno_mesh* raw, int64_t* mesh_id) {
   std::unique_ptr<SMesh> sm(new (std::nothrow) SMesh());
   if (!sm) {
     cweno_mesh_destroy(raw);
@@ -450,7 +450,7 @@ cweno_status cweno_server_register(cweno_server* s, int dim, int64_t n_vertices,
   std::vector<int32_t>().swap(m->op.gidx);
   std::vector<uint8_t>().swap(m->op.secpos);
   m->flags &= ~(unsigned)CWENO_FLAG_HOST_ONLY;
-  m->ops = o.ops;
+  m->ops = s->f32 ? CWENO_OPS_F32 : CWENO_OPS_F64;
   m->device = s->device;
   m->owns_device = false;
   m->device_bytes = (int64_t)sm->lay.total;
@@ -464,6 +464,35 @@ cweno_status cweno_server_register(cweno_server* s, int dim, int64_t n_vertices,
   *mesh_id = (int64_t)s->meshes.size();
   s->meshes.push_back(std::move(sm));
   return CWENO_OK;
+}
+
+}  // namespace
+
+cweno_status cweno_server_register(cweno_server* s, int dim, int64_t n_vertices, const double* vertices,
+                                   int64_t n_cells, const int32_t* cells, int degree, const cweno_options* opt,
+                                   int64_t* mesh_id) {
+  if (!s || !mesh_id) return fail(CWENO_E_ARG, "server and mesh_id must not be NULL");
+  cweno_options o{};
+  if (opt) o = *opt;
+  o.flags |= CWENO_FLAG_HOST_ONLY;
+  o.ops = s->f32 ? CWENO_OPS_F32 : CWENO_OPS_F64;
+  cweno_mesh* raw = nullptr;
+  if (cweno_status st = cweno_mesh_create(dim, n_vertices, vertices, n_cells, cells, degree, &o, nullptr, &raw))
+    return st;
+  return adopt(s, raw, mesh_id);
+}
+
+cweno_status cweno_server_register_mesh(cweno_server* s, const cweno_mesh* host_mesh, int64_t* mesh_id) {
+  if (!s || !mesh_id || !host_mesh) return fail(CWENO_E_ARG, "server, mesh and mesh_id must not be NULL");
+  if (!(host_mesh->flags & CWENO_FLAG_HOST_ONLY) || host_mesh->op.pinv.empty())
+    return fail(CWENO_E_ARG, "register_mesh takes a host-only mesh (built with CWENO_FLAG_HOST_ONLY)");
+  cweno_mesh* copy = nullptr;
+  try {
+    copy = new cweno_mesh(*host_mesh);
+  } catch (const std::bad_alloc&) {
+    return fail(CWENO_E_NOMEM, "host allocation failed");
+  }
+  return adopt(s, copy, mesh_id);
 }
 
 cweno_status cweno_server_mesh_info(cweno_server* s, int64_t mesh_id, int64_t* n_cells, int* n_basis,
