@@ -36,7 +36,7 @@ __device__ __forceinline__ void load_rows(T (&r)[KC][NL], const T* pinv, int64_t
     const int k = k0 + kk;
     const rsrc_t rk = make_rsrc(pinv + (int64_t)k * NL * Np, NL * prow);
 #pragma unroll
-    for (int l = 0; l < NL; ++l) r[kk][l] = k < NE1 ? bld<T>(rk, io, (uint32_t)l * prow) : T(0);
+    for (int l = 0; l < NL; ++l) r[kk][l] = k < NE1 ? bld_stream<T>(rk, io, (uint32_t)l * prow) : T(0);
   }
 }
 

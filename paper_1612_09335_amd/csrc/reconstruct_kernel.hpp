@@ -107,6 +107,11 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
+// Cache policy of streams touched once per launch (operator rows read,
+// coefficient rows written): non-temporal, so that they do not evict the
+// neighbour averages that the halo staging re-reads from L2.
+constexpr int kStream = 2;
+
 // Load/store at byte offset voff (per lane) + soff (wave-uniform).
 template <typename T> __device__ __forceinline__ T bld(rsrc_t r, uint32_t voff, uint32_t soff);
 template <> __device__ __forceinline__ double bld<double>(rsrc_t r, uint32_t voff, uint32_t soff) {
@@ -124,11 +129,20 @@ template <> __device__ __forceinline__ uint16_t bld<uint16_t>(rsrc_t r, uint32_t
 template <> __device__ __forceinline__ uint8_t bld<uint8_t>(rsrc_t r, uint32_t voff, uint32_t soff) {
   return __builtin_amdgcn_raw_buffer_load_b8(r, voff, soff, 0);
 }
+// Operator-row load, streamed (read once per launch).
+template <typename T> __device__ __forceinline__ T bld_stream(rsrc_t r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ double bld_stream<double>(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kStream));
+}
+template <> __device__ __forceinline__ float bld_stream<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, kStream));
+}
+// Coefficient-row store, streamed (written once per launch).
 __device__ __forceinline__ void bst(rsrc_t r, double x, uint32_t voff, uint32_t soff) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, soff, kStream);
 }
 __device__ __forceinline__ void bst(rsrc_t r, float x, uint32_t voff, uint32_t soff) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, voff, soff, kStream);
 }
 
 // Load from a wave-uniform base plus a 32-bit per-lane byte offset (gathers).
@@ -228,7 +242,7 @@ __device__ __forceinline__ void load_binv(const T* binv, int64_t Np, uint32_t io
 #pragma unroll
     for (int l = 0; l < D; ++l)
 #pragma unroll
-      for (int a = 0; a < D; ++a) bv[s][l][a] = bld<T>(rb, io, (uint32_t)((s * D + l) * D + a) * prow);
+      for (int a = 0; a < D; ++a) bv[s][l][a] = bld_stream<T>(rb, io, (uint32_t)((s * D + l) * D + a) * prow);
 }
 
 // Steps (b)-(e) for one cell and one variable, given P_opt's coefficients
@@ -389,7 +403,7 @@ __global__ __launch_bounds__(kThreads) void reconstruct_kernel(KParams<T> p, CWE
       const int k = k0 + kk;
       const rsrc_t rk = make_rsrc(p.pinv + (int64_t)k * NL * Np, NL * prow);
 #pragma unroll
-      for (int l = 0; l < NL; ++l) rr[kk][l] = k < NE1 ? bld<T>(rk, io, (uint32_t)l * prow) : T(0);
+      for (int l = 0; l < NL; ++l) rr[kk][l] = k < NE1 ? bld_stream<T>(rk, io, (uint32_t)l * prow) : T(0);
     }
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
