@@ -40,15 +40,16 @@ __device__ __forceinline__ void load_rows(T (&r)[KC][NL], const T* pinv, int64_t
   }
 }
 
-// Halo positions of stencil entries k0 .. k0+KC-1; entries past the stencil
-// point at the cell itself, so that their differences are exactly zero.
+// Halo positions of stencil entries k0 .. k0+KC-1 (a stream read once per
+// launch); entries past the stencil point at the cell itself, so that their
+// differences are exactly zero.
 template <int KC>
 __device__ __forceinline__ void load_pos(uint32_t (&h)[KC], rsrc_t rl, uint32_t lrow, int NE1, int k0, uint32_t io2,
                                          uint32_t self) {
 #pragma unroll
   for (int kk = 0; kk < KC; ++kk) {
     const int k = k0 + kk;
-    h[kk] = k < NE1 ? (uint32_t)bld<uint16_t>(rl, io2, (uint32_t)k * lrow) : self;
+    h[kk] = k < NE1 ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rl, io2, (uint32_t)k * lrow, kStream) : self;
   }
 }
 

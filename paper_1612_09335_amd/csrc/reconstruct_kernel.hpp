@@ -107,9 +107,9 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
-// Cache policy of streams touched once per launch (operator rows read,
-// coefficient rows written): non-temporal, so that they do not evict the
-// neighbour averages that the halo staging re-reads from L2.
+// Cache policy of streams touched once per launch (operator and halo-position
+// rows read, coefficient rows written): non-temporal, so that they do not
+// evict the neighbour averages that the halo staging re-reads from L2.
 constexpr int kStream = 2;
 
 // Load/store at byte offset voff (per lane) + soff (wave-uniform).
