@@ -99,6 +99,21 @@ def time_path(torch, mesh, q, steps, warmup, tune=True):
     return dict(total_ms=total, per_ms=per, wall_s=wall, out=out)
 
 
+def time_flushed(torch, mesh, q, out, steps, flush):
+    """Per-launch ms with a 1 GiB overwrite between launches (the 256 MB
+    Infinity Cache and the L2s hold none of the operators when a launch starts)."""
+    times = []
+    for _ in range(steps):
+        flush.fill_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        mesh.reconstruct(q, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times))
+
+
 def measure(torch, C, m, Q, M, factor, steps, warmup, label, d):
     """Time both precisions on one workload; returns per-precision records."""
     dev = torch.device("cuda:0")
@@ -118,15 +133,20 @@ def measure(torch, C, m, Q, M, factor, steps, warmup, label, d):
         ms = r["total_ms"] / steps
         kern_ms = float(np.mean(r["per_ms"]))
         achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
+        flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        ms_flushed = time_flushed(torch, lm, q, r["out"], max(10, steps // 5), flush)
+        del flush
         res[tag] = dict(
             value=m.n_cells * nv / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms,
+            flushed_ms=ms_flushed, flushed_frac=bytes_launch / (ms_flushed * 1e-3) / 1e9 / HBM_PEAK_GBS,
             latency_ms=dict(p50=float(np.percentile(r["per_ms"], 50)), p99=float(np.percentile(r["per_ms"], 99))),
             roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                           frac=achieved / HBM_PEAK_GBS, traffic=None,
                           algorithmic_bytes_per_cell=bpc, algorithmic_bytes_per_launch=bytes_launch),
             variant=lm.get_variant(tag, min(nv, 9)))
         log(f"{label} {tag}: variant {res[tag]['variant']}, {ms:.4f} ms/step, {res[tag]['value']:.3e} cells*vars/s, "
-            f"{achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}% of peak)")
+            f"{achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}% of peak); cache-flushed launch "
+            f"{ms_flushed:.4f} ms ({100 * res[tag]['flushed_frac']:.1f}%)")
     return res
 
 
@@ -340,7 +360,7 @@ def main():
             "precompute_s": r3["precompute_s"]}
         for tag in ("f64", "f32"):
             extras["kuhn64_M3_nv5"][tag] = {k: r3[tag][k] for k in ("value", "ms_per_step", "latency_ms", "roofline",
-                                                                   "variant")}
+                                                                   "variant", "flushed_ms", "flushed_frac")}
         del r3
         if not args.no_batch:
             try:
@@ -373,6 +393,10 @@ def main():
                    "lambda0": 0.95, "eps": 1e-14, "r": 4, "seed": SEED},
         "roofline": r64["roofline"],
         "latency_ms": r64["latency_ms"],
+        "cache_flushed": {"f64_ms": r64["flushed_ms"], "f64_frac": r64["flushed_frac"],
+                          "f32_ms": res["f32"]["flushed_ms"], "f32_frac": res["f32"]["flushed_frac"],
+                          "note": "median single launch after a 1 GiB overwrite; value and roofline are "
+                                  "back-to-back launches"},
         "kernel_variant": {"f64": res["f64"]["variant"], "f32": res["f32"]["variant"]},
         "fp32": {"value": res["f32"]["value"], "ms_per_step": res["f32"]["ms_per_step"],
                  "latency_ms": res["f32"]["latency_ms"], "roofline": res["f32"]["roofline"],
