@@ -110,6 +110,10 @@ void sigma_matrix(int d, int M, std::vector<double>& S);   // [nb][nb]
 // Grundmann-Moller rule exact to `degree`: barycentric points [q][d+1], weights sum 1.
 void grundmann_moller(int d, int degree, std::vector<double>& lam, std::vector<double>& w);
 
+// Integer part of the operators: gather lists (the central stencil without
+// the cell, then sector cells outside it, padded with the cell), their length
+// G, the sector positions in them, and the universal Sigma.
+void build_gather(const Geometry& g, const Stencils& st, int M, Operators& op);
 void build_operators(const Geometry& g, const Stencils& st, int M, Operators& op);
 
 }  // namespace cweno

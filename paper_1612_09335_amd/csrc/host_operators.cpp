@@ -178,7 +178,7 @@ bool pseudo_inverse(int m, int n, const double* A, double* P) {
 
 }  // namespace
 
-void build_operators(const Geometry& g, const Stencils& st, int M, Operators& op) {
+void build_gather(const Geometry& g, const Stencils& st, int M, Operators& op) {
   const int d = g.d, ns = d + 1, nb = n_basis(M, d), n_e = st.n_e, NE1 = n_e - 1;
   op.d = d;
   op.M = M;
@@ -206,11 +206,28 @@ void build_operators(const Geometry& g, const Stencils& st, int M, Operators& op
   op.nc = g.nc;
   op.Np = (g.nc + 63) / 64 * 64;
   const size_t Np = (size_t)op.Np;
-  op.pinv.assign((size_t)(nb - 1) * NE1 * Np, 0.0);
-  op.binv.assign((size_t)ns * d * d * Np, 0.0);
   op.gidx.assign((size_t)G * Np, 0);
   op.secpos.assign((size_t)ns * d * Np, 0);
   op.mask.assign(Np, 0);
+  parallel_for(g.nc, [&](int64_t b, int64_t e) {
+    std::vector<int32_t> list(G);
+    for (int64_t i = b; i < e; ++i) {
+      const int32_t* S0 = &st.central[(size_t)i * n_e];
+      int nl = 0;
+      for (int k = 1; k < n_e; ++k) list[nl++] = S0[k];
+      for (int32_t j : extras[i]) list[nl++] = j;
+      for (int k = nl; k < G; ++k) list[k] = (int32_t)i;
+      for (int k = 0; k < G; ++k) op.gidx[(size_t)k * Np + i] = list[k];
+      for (int s = 0; s < ns; ++s) {
+        const int32_t* sec = &st.sectors[((size_t)i * ns + s) * ns];
+        if (sec[0] < 0) continue;
+        for (int a = 0; a < d; ++a) {
+          const int k = (int)(std::find(list.begin(), list.begin() + nl, sec[a + 1]) - list.begin());
+          op.secpos[(size_t)(s * d + a) * Np + i] = (uint8_t)k;
+        }
+      }
+    }
+  });
   sigma_matrix(d, M, op.sigma);
   {  // drop row/column 0 (the constant has no derivatives)
     std::vector<double> s2((size_t)(nb - 1) * (nb - 1));
@@ -218,6 +235,14 @@ void build_operators(const Geometry& g, const Stencils& st, int M, Operators& op
       for (int m = 1; m < nb; ++m) s2[(size_t)(l - 1) * (nb - 1) + (m - 1)] = op.sigma[(size_t)l * nb + m];
     op.sigma.swap(s2);
   }
+}
+
+void build_operators(const Geometry& g, const Stencils& st, int M, Operators& op) {
+  build_gather(g, st, M, op);
+  const int d = g.d, ns = d + 1, nb = op.nb, n_e = st.n_e, NE1 = n_e - 1, G = op.G;
+  const size_t Np = (size_t)op.Np;
+  op.pinv.assign((size_t)(nb - 1) * NE1 * Np, 0.0);
+  op.binv.assign((size_t)ns * d * d * Np, 0.0);
   std::vector<double> qlam, qw;
   grundmann_moller(d, M, qlam, qw);
   const int nq = (int)qw.size();
@@ -232,11 +257,9 @@ void build_operators(const Geometry& g, const Stencils& st, int M, Operators& op
       for (int r = 0; r < d; ++r)
         for (int c = 0; c < d; ++c) J[r * d + c] = Xi[(c + 1) * d + r] - Xi[r];
       if (!invert(d, J, Jinv)) throw Error(CWENO_E_MESH, "singular cell map at cell " + std::to_string(i));
-      const int32_t* S0 = &st.central[(size_t)i * n_e];
-      int nl = 0;
-      for (int k = 1; k < n_e; ++k) list[nl++] = S0[k];
-      for (int32_t j : extras[i]) list[nl++] = j;
-      for (int k = nl; k < G; ++k) list[k] = (int32_t)i;
+      for (int k = 0; k < G; ++k) list[k] = op.gidx[(size_t)k * Np + i];
+      int nl = G;
+      while (nl > NE1 && list[nl - 1] == (int32_t)i) --nl;   // padding entries are the cell itself
       // averages of psi_1.. over every gathered cell, in cell i's frame
       for (int k = 0; k < nl; ++k) {
         int64_t j = list[k];
@@ -270,24 +293,19 @@ void build_operators(const Geometry& g, const Stencils& st, int M, Operators& op
         throw Error(CWENO_E_RANK, "rank-deficient least-squares system at cell " + std::to_string(i));
       for (int l = 0; l < nb - 1; ++l)   // device layout is k-major: row k*(nb-1) + l
         for (int k = 0; k < NE1; ++k) op.pinv[((size_t)k * (nb - 1) + l) * Np + i] = P[(size_t)l * NE1 + k];
-      for (int k = 0; k < G; ++k) op.gidx[(size_t)k * Np + i] = list[k];
       uint8_t mask = 0;
       for (int s = 0; s < ns; ++s) {
         const int32_t* sec = &st.sectors[((size_t)i * ns + s) * ns];
         if (sec[0] < 0) { dropped_per_cell[i]++; continue; }
         double B[9], Binv[9];
-        int pos[3];
         for (int a = 0; a < d; ++a) {
-          int32_t j = sec[a + 1];
-          int k = (int)(std::find(list.begin(), list.begin() + nl, j) - list.begin());
-          pos[a] = k;
+          const int k = op.secpos[(size_t)(s * d + a) * Np + i];
           for (int l = 0; l < d; ++l) B[a * d + l] = A[(size_t)k * (nb - 1) + l];
         }
         if (!(cond2(d, B) <= kSectorCondMax) || !invert(d, B, Binv)) { dropped_per_cell[i]++; continue; }
         mask |= (uint8_t)(1u << s);
         for (int l = 0; l < d; ++l)
           for (int a = 0; a < d; ++a) op.binv[(size_t)((s * d + l) * d + a) * Np + i] = Binv[l * d + a];
-        for (int a = 0; a < d; ++a) op.secpos[(size_t)(s * d + a) * Np + i] = (uint8_t)pos[a];
       }
       op.mask[i] = mask;
     }

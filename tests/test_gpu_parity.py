@@ -142,3 +142,26 @@ def test_every_variant_bitwise_identical(case):
             idx = np.arange(0, m.n_cells, 7)
             err = data_scaled_error(base["coeffs"][:, :, idx], ref["coeffs"], Q, lm.tables()["stencil"][idx])
             assert err <= TOL64
+
+
+def test_more_variables_than_one_block_and_argument_errors():
+    """11 variables run as several variable blocks; overlapping or missing
+    buffers are refused before any launch."""
+    torch = torch_cuda()
+    C = _lib()
+    m = tri_mesh(12, 0.15, 51)
+    rng = np.random.default_rng(52)
+    Q = rng.normal(size=(11, m.n_cells)) + 2.0 * (rng.random((1, m.n_cells)) < 0.3)
+    lm, res = _check_f64(m, 2, Q)
+    q = torch.tensor(Q, dtype=torch.float64, device="cuda:0")
+    out = torch.empty((11, lm.n_basis, lm.n_cells), dtype=torch.float64, device="cuda:0")
+    lib = C.lib
+    # coefficients overlapping the averages
+    big = torch.empty(11 * lm.n_basis * lm.n_cells + 11 * lm.n_cells, dtype=torch.float64, device="cuda:0")
+    st = lib.cweno_reconstruct(lm._h, 11, C.F64, big.data_ptr(), big.data_ptr() + 8 * 5, None, None, None)
+    assert st == -1 and b"overlap" in lib.cweno_last_error()
+    # missing buffers, zero variables, wrong precision for the operators held
+    assert lib.cweno_reconstruct(lm._h, 11, C.F64, None, out.data_ptr(), None, None, None) == -1
+    assert lib.cweno_reconstruct(lm._h, 0, C.F64, q.data_ptr(), out.data_ptr(), None, None, None) == -1
+    assert lib.cweno_reconstruct(lm._h, 11, C.F32, q.data_ptr(), out.data_ptr(), None, None, None) == -1
+
