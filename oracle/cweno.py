@@ -81,7 +81,12 @@ def linear_weights(d: int, lambda0) -> np.ndarray:
 class CwenoOracle:
     """Plain FP64 CWENO reconstruction of one mesh."""
 
-    def __init__(self, vertices, cells, box, opts: Options, nbr=None):
+    def __init__(self, vertices, cells, box, opts: Options, nbr=None, stencils=None):
+        """``stencils``: optional fixed tables (central [n, n_e], sectors
+        [n, d+1, d+1] with rows of -1 for unfilled sectors) used instead of
+        selecting stencils on this geometry -- a moving mesh keeps the
+        stencils of its connectivity while its vertices move, and only the
+        reconstruction matrices change (Sec. 2.1 on ALE meshes)."""
         self.V = np.asarray(vertices, dtype=np.float64)
         self.Cells = np.asarray(cells, dtype=np.int64)
         self.d = int(self.V.shape[1])
@@ -96,11 +101,22 @@ class CwenoOracle:
         self.qw_avg = self.qw / self.qw.sum()
         self.lam = linear_weights(self.d, opts.lambda0)
         self._stencil_cache = {}
+        self._fixed = None
+        if stencils is not None:
+            central, sectors = stencils
+            self._fixed = (np.asarray(central, dtype=np.int64), np.asarray(sectors, dtype=np.int64))
+            if self._fixed[0].shape != (self.Cells.shape[0], self.n_e):
+                raise ValueError("fixed central stencils must be [n_cells, n_e]")
 
     # ------------------------------------------------------------ tables
     def stencils(self, i: int):
         """(central stencil list, list of d+1 sector lists or None)."""
         c = self._stencil_cache.get(i)
+        if c is None and self._fixed is not None:
+            S0 = [int(j) for j in self._fixed[0][i]]
+            Ss = [None if row[0] < 0 else [int(j) for j in row] for row in self._fixed[1][i]]
+            c = (S0, Ss)
+            self._stencil_cache[i] = c
         if c is None:
             S0 = central_stencil(self.geo, self.nbr, i, self.n_e)
             Ss = sector_stencils(self.geo, self.nbr, i, self.opts.sector_rule)

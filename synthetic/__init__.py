@@ -10,13 +10,13 @@ unit square and Kuhn tetrahedrisations of the unit cube, Sec. 3); the fields
 mimic its states (Euler variables with a Sod-type jump, Sec. 3.2; ideal-MHD
 shaped nine-variable states, Sec. 3.3; a spherical blast).
 """
-from .meshes import SimplexMesh, batch_spec, tri_mesh, kuhn_tet_mesh, workload_mesh
+from .meshes import SimplexMesh, batch_spec, moved_vertices, tri_mesh, kuhn_tet_mesh, workload_mesh
 from .fields import (cell_averages, euler2d_sod_circle, mhd2d_fourier_jump,
                      euler3d_blast, random_polynomial, polynomial_field,
                      smooth_fourier_field, workload_fields)
 
 __all__ = [
-    "SimplexMesh", "batch_spec", "tri_mesh", "kuhn_tet_mesh", "workload_mesh",
+    "SimplexMesh", "batch_spec", "moved_vertices", "tri_mesh", "kuhn_tet_mesh", "workload_mesh",
     "cell_averages", "euler2d_sod_circle", "mhd2d_fourier_jump",
     "euler3d_blast", "random_polynomial", "polynomial_field",
     "smooth_fourier_field", "workload_fields",

@@ -187,3 +187,20 @@ def batch_spec(n_meshes: int = 64, lo: float = 1e3, hi: float = 3e5, seed: int =
         M = int(rng.integers(2, 5))
         out.append((d, int(round(n)), M, seed + 1 + t))
     return out
+
+
+def moved_vertices(mesh: SimplexMesh, amplitude: float = 0.3, phase: float = 0.0) -> np.ndarray:
+    """Vertex positions of ``mesh`` after a smooth periodic motion.
+
+    Each axis is sheared by a sine of the next axis (cyclically):
+    x_a += amplitude / (2 pi) * sin(2 pi (x_{a+1} + phase)), so the motion
+    is periodic on the unit box, its gradient is at most ``amplitude`` and
+    the Jacobian stays invertible (1 - amplitude^2 > 0 in 2-D,
+    1 - amplitude^3 > 0 in 3-D).  The connectivity is unchanged.
+    """
+    V = np.asarray(mesh.vertices, dtype=np.float64)
+    d = V.shape[1]
+    out = V.copy()
+    for a in range(d):
+        out[:, a] += amplitude / (2 * np.pi) * np.sin(2 * np.pi * (V[:, (a + 1) % d] + phase))
+    return out
