@@ -61,7 +61,8 @@ typedef enum {
 typedef enum {
   CWENO_OPS_F64 = 0,
   CWENO_OPS_F32 = 1,
-  CWENO_OPS_BOTH = 2
+  CWENO_OPS_BOTH = 2,
+  CWENO_OPS_NONE = 3   /* no stored operators (a moving mesh: see cweno_reconstruct_moving) */
 } cweno_ops;
 
 typedef enum {
@@ -78,6 +79,8 @@ typedef enum {
 #define CWENO_FLAG_HOST_ONLY 1u       /* build tables/operators on the host only; no device upload */
 #define CWENO_FLAG_SIGMA0_POPT 2u     /* indicator of the central polynomial from P_opt, not P_0   */
 #define CWENO_FLAG_LINEAR_WEIGHTS 4u  /* diagnostic: omega := lambda (w = P_opt)                   */
+#define CWENO_FLAG_MOVING 8u          /* keep connectivity and stencils on the device for
+                                         cweno_reconstruct_moving                                */
 
 /* Reconstruction options.  A zero-initialised struct gives the defaults. */
 typedef struct {
@@ -196,6 +199,47 @@ cweno_status cweno_mesh_operators(const cweno_mesh* mesh, int64_t cell, double* 
 cweno_status cweno_reconstruct(const cweno_mesh* mesh, int n_vars, cweno_dtype dtype,
                                const void* q, void* coeffs, void* sigma, void* omega,
                                void* hip_stream);
+
+/*
+ * cweno_reconstruct_moving -- the same reconstruction on a moving mesh: the
+ * per-cell operators are rebuilt on the device from this call's vertex
+ * positions instead of being read from memory (on an ALE mesh the
+ * reconstruction matrices change with the geometry at every step, Sec. 2.1).
+ *
+ * The connectivity, the central and sectorial stencils and each cell's
+ * reference frame (its vertex order) are those fixed at cweno_mesh_create;
+ * only the vertex positions change.  Per cell and call the kernel computes,
+ * in FP64: the cell's reference map from the moved vertices (minimum image
+ * across periodic axes), the averages of psi_1 .. psi_{n_basis-1} over every
+ * stencil cell in that frame (Grundmann-Moller quadrature exact to degree M),
+ * the least-squares solve of eq. CWENO:Popt by Householder QR of the column-
+ * scaled matrix, the sectorial systems of eq. CWENO:Ps from the linear basis
+ * functions at the sector cells' barycentres (a sector whose system has
+ * 2-norm condition number above 1e10 is dropped for this call), and then
+ * P_0, the indicators, the weights and the blend exactly as
+ * cweno_reconstruct does.  Nothing is stored between calls.
+ *
+ *  mesh      created with CWENO_FLAG_MOVING (any ops, CWENO_OPS_NONE keeps
+ *            no stored operators at all); its central stencil may hold at
+ *            most 129 cells
+ *  vertices  device, [n_vertices][dim] doubles: this call's positions
+ *  n_vars, dtype, q, coeffs, sigma, omega
+ *            as for cweno_reconstruct (FP32 averages and coefficients are
+ *            converted to and from FP64 around the arithmetic; coefficient 0
+ *            is the cell's own average, bit for bit)
+ *  fault     optional device int: the kernel ORs 1 into it for a cell whose
+ *            moved vertices give a singular reference map and 2 for a zero
+ *            column or a rank-deficient least-squares system (R diagonal at
+ *            or below 1e-12 of its largest entry); such a cell's outputs are
+ *            not meaningful.  The caller clears it.  NULL: no report.
+ *  hip_stream  stream of the launch (NULL = default); asynchronous
+ *
+ * No buffer may overlap another.  Errors: CWENO_E_ARG (bad arguments, a mesh
+ * without CWENO_FLAG_MOVING, a stencil too large), CWENO_E_HIP.
+ */
+cweno_status cweno_reconstruct_moving(const cweno_mesh* mesh, const double* vertices, int n_vars,
+                                      cweno_dtype dtype, const void* q, void* coeffs, void* sigma,
+                                      void* omega, int* fault, void* hip_stream);
 
 /*
  * Kernel variants and their autotuner.

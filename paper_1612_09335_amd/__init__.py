@@ -17,16 +17,17 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcweno.so")
 
 F64, F32 = 0, 1
-OPS = {"f64": 0, "f32": 1, "both": 2}
+OPS = {"f64": 0, "f32": 1, "both": 2, "none": 3}
 SECTOR_RULES = {"cone": 0, "face": 1}
-FLAG_HOST_ONLY, FLAG_SIGMA0_POPT, FLAG_LINEAR_WEIGHTS = 1, 2, 4
+FLAG_HOST_ONLY, FLAG_SIGMA0_POPT, FLAG_LINEAR_WEIGHTS, FLAG_MOVING = 1, 2, 4, 8
 
 STATUS = {0: "CWENO_OK", -1: "CWENO_E_ARG", -2: "CWENO_E_MESH", -3: "CWENO_E_STENCIL",
           -4: "CWENO_E_RANK", -5: "CWENO_E_PERIODIC", -6: "CWENO_E_NOMEM", -7: "CWENO_E_BUDGET",
           -8: "CWENO_E_HIP", -9: "CWENO_E_BUSY", -10: "CWENO_E_CANCELLED"}
 
 SYMBOLS = ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_mesh_tables",
-           "cweno_mesh_operators", "cweno_reconstruct", "cweno_status_string", "cweno_last_error",
+           "cweno_mesh_operators", "cweno_reconstruct", "cweno_reconstruct_moving", "cweno_status_string",
+           "cweno_last_error",
            "cweno_abi_version", "cweno_num_variants", "cweno_mesh_set_variant", "cweno_mesh_get_variant",
            "cweno_mesh_tune", "cweno_batch_create", "cweno_batch_run", "cweno_batch_info", "cweno_batch_group",
            "cweno_batch_destroy", "cweno_server_create", "cweno_server_register", "cweno_server_register_mesh",
@@ -68,6 +69,7 @@ def _load():
     lib.cweno_mesh_tables.argtypes = [vp, vp, vp, vp]
     lib.cweno_mesh_operators.argtypes = [vp, i64, vp, vp, vp]
     lib.cweno_reconstruct.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
+    lib.cweno_reconstruct_moving.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp]
     lib.cweno_mesh_set_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.cweno_mesh_get_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -131,7 +133,7 @@ class Mesh:
     def __init__(self, vertices, cells, degree: int, periodic=(0.0, 0.0, 0.0), stencil_factor: float = 0.0,
                  lambda0: float = 0.0, eps: float = 0.0, r: int = 0, ops: str = "f64",
                  sector_rule: str = "cone", sigma0_popt: bool = False, linear_weights: bool = False,
-                 host_only: bool = False, stream=None):
+                 host_only: bool = False, moving: bool = False, stream=None):
         V = np.ascontiguousarray(vertices, dtype=np.float64)
         C = np.ascontiguousarray(cells, dtype=np.int32)
         self.dim = int(V.shape[1])
@@ -146,7 +148,9 @@ class Mesh:
         o.ops = OPS[ops]
         o.sector_rule = SECTOR_RULES[sector_rule]
         o.flags = ((FLAG_HOST_ONLY if host_only else 0) | (FLAG_SIGMA0_POPT if sigma0_popt else 0)
-                   | (FLAG_LINEAR_WEIGHTS if linear_weights else 0))
+                   | (FLAG_LINEAR_WEIGHTS if linear_weights else 0) | (FLAG_MOVING if moving else 0))
+        self.n_vertices = int(V.shape[0])
+        self.moving = moving
         self.ops = ops
         self.host_only = host_only
         h = ctypes.c_void_p()
@@ -218,6 +222,36 @@ class Mesh:
                                      None if omega is None else omega.data_ptr(), _stream_ptr(stream)))
         return out
 
+    def reconstruct_moving(self, vertices, q, out=None, sigma=None, omega=None, fault=None, stream=None):
+        """cweno_reconstruct_moving: operators rebuilt from ``vertices`` (CUDA float64
+        [n_vertices, dim]) for this call; otherwise as ``reconstruct``.  ``fault`` may be
+        a CUDA int32 tensor of one element that the kernel ORs its fault bits into."""
+        import torch
+        if not q.is_cuda or q.dim() != 2 or q.shape[1] != self.n_cells or not q.is_contiguous():
+            raise ValueError("q must be a contiguous CUDA tensor [n_vars, n_cells]")
+        if (not vertices.is_cuda or vertices.dtype != torch.float64 or not vertices.is_contiguous()
+                or tuple(vertices.shape) != (self.n_vertices, self.dim)):
+            raise ValueError(f"vertices must be a contiguous CUDA float64 tensor [{self.n_vertices}, {self.dim}]")
+        dt = {torch.float64: F64, torch.float32: F32}.get(q.dtype)
+        if dt is None:
+            raise ValueError("q must be float64 or float32")
+        nv = q.shape[0]
+        if out is None:
+            out = torch.empty((nv, self.n_basis, self.n_cells), dtype=q.dtype, device=q.device)
+        for t, shape in ((out, (nv, self.n_basis, self.n_cells)), (sigma, (nv, self.dim + 2, self.n_cells)),
+                         (omega, (nv, self.dim + 2, self.n_cells))):
+            if t is not None and (tuple(t.shape) != shape or t.dtype != q.dtype or not t.is_contiguous()
+                                  or t.device != q.device):
+                raise ValueError(f"output tensor must be contiguous {q.dtype} {shape} on {q.device}")
+        if fault is not None and (not fault.is_cuda or fault.dtype != torch.int32 or fault.numel() < 1):
+            raise ValueError("fault must be a CUDA int32 tensor")
+        if stream is None:
+            stream = torch.cuda.current_stream(q.device)
+        _check(lib.cweno_reconstruct_moving(self._h, vertices.data_ptr(), nv, dt, q.data_ptr(), out.data_ptr(),
+                                            None if sigma is None else sigma.data_ptr(),
+                                            None if omega is None else omega.data_ptr(),
+                                            None if fault is None else fault.data_ptr(), _stream_ptr(stream)))
+        return out
 
     # ---------------------------------------------------------------- variants
     def set_variant(self, dtype: str, vb: int, variant: int):

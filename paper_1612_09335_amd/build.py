@@ -23,9 +23,10 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["host_geometry.cpp", "host_basis.cpp", "host_operators.cpp", "host_halo.cpp"]
-HIP_SOURCES = ["abi.hip", "batch.hip", "server.hip"]
-# kernels.hip is compiled once per (precision, dimension, degree)
+HIP_SOURCES = ["abi.hip", "batch.hip", "server.hip", "moving.hip"]
+# kernels.hip and moving_kernels.hip are compiled once per (precision, dimension, degree)
 KERNEL_UNITS = [(tn, d, m) for tn in ("f64", "f32") for d in (2, 3) for m in (1, 2, 3, 4)]
+KERNEL_FILES = ["kernels", "moving_kernels"]
 
 # Integer tables depend on exact floating-point comparisons: no contraction.
 HOST_FLAGS = ["-std=c++17", "-O3", "-fPIC", "-pthread", "-ffp-contract=off", "-Wall", "-Wextra",
@@ -63,10 +64,13 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         obj = os.path.join(BUILD, src + ".o")
         cmds.append([HIPCC, *HIP_FLAGS, f"-I{BUILD}", "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    for tn, d, m in KERNEL_UNITS:
-        obj = os.path.join(BUILD, f"kernels_{tn}_d{d}_m{m}.o")
+    # the heaviest units first, so that they do not finish last on their own
+    units = sorted(((f, tn, d, m) for f in KERNEL_FILES for tn, d, m in KERNEL_UNITS),
+                   key=lambda u: (u[0] != "moving_kernels", -u[2], -u[3]))
+    for f, tn, d, m in units:
+        obj = os.path.join(BUILD, f"{f}_{tn}_d{d}_m{m}.o")
         cmds.append([HIPCC, *HIP_FLAGS, f"-I{BUILD}", f"-DCWENO_TN={tn}", f"-DCWENO_D={d}", f"-DCWENO_M={m}", "-c",
-                     os.path.join(CSRC, "kernels.hip"), "-o", obj])
+                     os.path.join(CSRC, f + ".hip"), "-o", obj])
         objs.append(obj)
     with cf.ThreadPoolExecutor(jobs) as ex:
         for cmd, out in zip(cmds, ex.map(_run, cmds)):

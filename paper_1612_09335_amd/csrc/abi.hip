@@ -50,6 +50,7 @@ using cweno_abi::variant_ok;
 using cweno_abi::default_variant;
 using cweno_abi::make_params;
 using cweno_abi::launch_block;
+using cweno_abi::overlap;
 
 namespace {
 
@@ -74,13 +75,6 @@ cweno_status upload_f32(DevBuf& b, const std::vector<double>& src, hipStream_t s
   std::vector<float> tmp(src.size());
   for (size_t t = 0; t < src.size(); ++t) tmp[t] = (float)src[t];
   return upload(b, tmp.data(), tmp.size() * sizeof(float), s, total);
-}
-
-// Whether [a, a + na) and [b, b + nb) share a byte (empty ranges never do).
-bool overlap(const void* a, uint64_t na, const void* b, uint64_t nb) {
-  if (!a || !b || !na || !nb) return false;
-  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
-  return x < y + nb && y < x + na;
 }
 
 cweno_status check_reconstruct_args(const cweno_mesh* m, int n_vars, cweno_dtype dtype, const void* q,
@@ -153,7 +147,9 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
   m->nc = n_cells;
   m->flags = o.flags;
   m->ops = o.ops;
-  if (o.ops < CWENO_OPS_F64 || o.ops > CWENO_OPS_BOTH) return fail(CWENO_E_ARG, "bad ops");
+  if (o.ops < CWENO_OPS_F64 || o.ops > CWENO_OPS_NONE) return fail(CWENO_E_ARG, "bad ops");
+  if ((o.flags & CWENO_FLAG_MOVING) && (o.flags & CWENO_FLAG_HOST_ONLY))
+    return fail(CWENO_E_ARG, "a moving mesh lives on the device; it cannot be host-only");
   if (o.sector_rule != CWENO_SECTOR_CONE && o.sector_rule != CWENO_SECTOR_FACE)
     return fail(CWENO_E_ARG, "bad sector rule");
   const double f = o.stencil_factor == 0.0 ? (double)dim : o.stencil_factor;
@@ -190,7 +186,7 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
     cweno::face_adjacency(in, m->nbr);
     cweno::Stencils st;
     cweno::build_stencils(g, m->nbr, m->n_e, o.sector_rule, st);
-    cweno::build_operators(g, st, degree, m->op);
+    if (o.ops != CWENO_OPS_NONE) cweno::build_operators(g, st, degree, m->op);
     m->central.swap(st.central);
     m->sectors.swap(st.sectors);
   } catch (const cweno::Error& e) {
@@ -200,8 +196,19 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
   } catch (const std::exception& e) {
     return fail(CWENO_E_ARG, e.what());
   }
+  if (o.ops == CWENO_OPS_NONE) {   // no stored operators: only the moving-mesh path can run
+    m->op.d = dim;
+    m->op.M = degree;
+    m->op.nb = m->nb;
+    m->op.n_e = m->n_e;
+    m->op.nc = n_cells;
+    m->op.Np = (n_cells + 63) / 64 * 64;
+    cweno::sigma_matrix(dim, degree, m->op.sigma);
+  }
   m->G = m->op.G;
   m->Np = m->op.Np;
+  for (int a = 0; a < 3; ++a) m->box[a] = a < dim ? o.periodic[a] : 0.0;
+  m->n_vertices = n_vertices;
   // the kernels address each block of operator or index rows with 32-bit byte offsets
   {
     const uint64_t Np = (uint64_t)m->Np, lim = uint64_t(1) << 32;
@@ -217,6 +224,20 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
     if (cweno_status cst = cweno_abi::configure_device_kernels()) return cst;
     const cweno::Operators& op = m->op;
     cweno_status st;
+    if (o.flags & CWENO_FLAG_MOVING) {
+      // connectivity, stencils and the quadrature rule for the moving-mesh kernel
+      std::vector<double> lam, w, rule;
+      cweno::grundmann_moller(dim, degree, lam, w);
+      m->nq = (int)w.size();
+      for (int k = 0; k < m->nq; ++k) {
+        for (int v = 0; v <= dim; ++v) rule.push_back(lam[(size_t)k * (dim + 1) + v]);
+        rule.push_back(w[k]);
+      }
+      if ((st = upload(m->mvC, cells, (size_t)n_cells * (dim + 1) * 4, s, m->device_bytes))) return st;
+      if ((st = upload(m->mvS0, m->central.data(), m->central.size() * 4, s, m->device_bytes))) return st;
+      if ((st = upload(m->mvSS, m->sectors.data(), m->sectors.size() * 4, s, m->device_bytes))) return st;
+      if ((st = upload(m->mvRule, rule.data(), rule.size() * 8, s, m->device_bytes))) return st;
+    }
     if (o.ops == CWENO_OPS_F64 || o.ops == CWENO_OPS_BOTH) {
       if ((st = upload(m->pinv64, op.pinv.data(), op.pinv.size() * 8, s, m->device_bytes))) return st;
       if ((st = upload(m->binv64, op.binv.data(), op.binv.size() * 8, s, m->device_bytes))) return st;
@@ -227,18 +248,20 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
       if ((st = upload_f32(m->binv32, op.binv, s, m->device_bytes))) return st;
       if ((st = upload_f32(m->sigma32, op.sigma, s, m->device_bytes))) return st;
     }
-    if ((st = upload(m->gidx, op.gidx.data(), op.gidx.size() * 4, s, m->device_bytes))) return st;
-    if ((st = upload(m->secpos, op.secpos.data(), op.secpos.size(), s, m->device_bytes))) return st;
-    if ((st = upload(m->mask, op.mask.data(), op.mask.size(), s, m->device_bytes))) return st;
-    try {
-      cweno::Halo h;
-      cweno::build_halo(op, cweno::kHaloBlock, h);
-      if ((st = upload(m->halo, h.cells.data(), h.cells.size() * 4, s, m->device_bytes))) return st;
-      if ((st = upload(m->hoff, h.offset.data(), h.offset.size() * 4, s, m->device_bytes))) return st;
-      if ((st = upload(m->lidx, h.lidx.data(), h.lidx.size() * 2, s, m->device_bytes))) return st;
-      m->maxH = h.max_len;
-    } catch (const cweno::Error&) {
-      m->maxH = 0;   // halos too large: the halo kernel is not used for this mesh
+    if (o.ops != CWENO_OPS_NONE) {
+      if ((st = upload(m->gidx, op.gidx.data(), op.gidx.size() * 4, s, m->device_bytes))) return st;
+      if ((st = upload(m->secpos, op.secpos.data(), op.secpos.size(), s, m->device_bytes))) return st;
+      if ((st = upload(m->mask, op.mask.data(), op.mask.size(), s, m->device_bytes))) return st;
+      try {
+        cweno::Halo h;
+        cweno::build_halo(op, cweno::kHaloBlock, h);
+        if ((st = upload(m->halo, h.cells.data(), h.cells.size() * 4, s, m->device_bytes))) return st;
+        if ((st = upload(m->hoff, h.offset.data(), h.offset.size() * 4, s, m->device_bytes))) return st;
+        if ((st = upload(m->lidx, h.lidx.data(), h.lidx.size() * 2, s, m->device_bytes))) return st;
+        m->maxH = h.max_len;
+      } catch (const cweno::Error&) {
+        m->maxH = 0;   // halos too large: the halo kernel is not used for this mesh
+      }
     }
     // the device holds the operators now; keep only what the host-side dumps need
     std::vector<double>().swap(m->op.pinv);

@@ -21,6 +21,13 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Whether [a, a + na) and [b, b + nb) share a byte (empty ranges never do).
+inline bool overlap(const void* a, uint64_t na, const void* b, uint64_t nb) {
+  if (!a || !b || !na || !nb) return false;
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
 // Raise the dynamic-LDS limit of every halo kernel once per device (before
 // any launch, so that launches may later be captured into graphs).
 cweno_status configure_device_kernels();
@@ -43,6 +50,12 @@ struct cweno_mesh {
   int device = -1;
   cweno_abi::DevBuf pinv64, binv64, sigma64, pinv32, binv32, sigma32, gidx, secpos, mask, halo, hoff, lidx;
   int maxH = 0;
+  // moving meshes: cell vertex ids, central and sector stencils (cell-major),
+  // quadrature rule [nq][d+2]
+  cweno_abi::DevBuf mvC, mvS0, mvSS, mvRule;
+  int nq = 0;
+  int64_t n_vertices = 0;
+  double box[3] = {0, 0, 0};
   int64_t device_bytes = 0;
   bool owns_device = true;   // false: the device buffers point into memory owned elsewhere (a server arena)
   // kernel variant (index into cweno::kVariants) per [precision][variable block]
@@ -51,7 +64,7 @@ struct cweno_mesh {
   ~cweno_mesh() {
     if (!owns_device) return;
     for (cweno_abi::DevBuf* b : {&pinv64, &binv64, &sigma64, &pinv32, &binv32, &sigma32, &gidx, &secpos, &mask, &halo,
-                                 &hoff, &lidx})
+                                 &hoff, &lidx, &mvC, &mvS0, &mvSS, &mvRule})
       if (b->p) (void)hipFree(b->p);
   }
 };

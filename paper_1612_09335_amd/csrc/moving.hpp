@@ -1,0 +1,64 @@
+// Launchers of the moving-mesh kernel: one translation unit per (precision,
+// dimension, degree) instantiates the segment shapes that fit that basis.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "moving_kernel.hpp"
+
+namespace cweno {
+
+// Segment shapes (lanes per cell, rows per lane) instantiated for (D, M): a
+// segment of 32 lanes when the basis leaves room for the rows, 64 lanes
+// always, and 64 lanes with two rows each for the wide 3-D stencils.
+__host__ __device__ constexpr bool move_shape_ok(int D, int M, int seg, int rpl) {
+  return (seg == 32 && rpl == 1 && nbasis_c(M, D) - 1 < 32) || (seg == 64 && rpl == 1) ||
+         (seg == 64 && rpl == 2 && D == 3 && M >= 2);
+}
+
+// Smallest instantiated shape whose rows hold the NE1 stencil cells besides
+// the cell; false if none does.
+inline bool move_shape(int D, int M, int NE1, int& seg, int& rpl) {
+  const int cand[3][2] = {{32, 1}, {64, 1}, {64, 2}};
+  for (const auto& c : cand)
+    if (move_shape_ok(D, M, c[0], c[1]) && NE1 <= c[0] * c[1]) {
+      seg = c[0];
+      rpl = c[1];
+      return true;
+    }
+  return false;
+}
+
+#define CWENO_DECL_MOVE(tn, T, d, m) \
+  hipError_t launch_moving_##tn##_d##d##_m##m(const MParams<T>& p, int seg, int rpl, hipStream_t s);
+#define CWENO_DECL_MOVE_ALL(tn, T)                                                                          \
+  CWENO_DECL_MOVE(tn, T, 2, 1) CWENO_DECL_MOVE(tn, T, 2, 2) CWENO_DECL_MOVE(tn, T, 2, 3)                    \
+  CWENO_DECL_MOVE(tn, T, 2, 4) CWENO_DECL_MOVE(tn, T, 3, 1) CWENO_DECL_MOVE(tn, T, 3, 2)                    \
+  CWENO_DECL_MOVE(tn, T, 3, 3) CWENO_DECL_MOVE(tn, T, 3, 4)
+CWENO_DECL_MOVE_ALL(f64, double)
+CWENO_DECL_MOVE_ALL(f32, float)
+#undef CWENO_DECL_MOVE_ALL
+#undef CWENO_DECL_MOVE
+
+#define CWENO_MOVE_CASES(tn)                                                             \
+  switch (d * 10 + m) {                                                                  \
+    case 21: return launch_moving_##tn##_d2_m1(p, seg, rpl, s);                          \
+    case 22: return launch_moving_##tn##_d2_m2(p, seg, rpl, s);                          \
+    case 23: return launch_moving_##tn##_d2_m3(p, seg, rpl, s);                          \
+    case 24: return launch_moving_##tn##_d2_m4(p, seg, rpl, s);                          \
+    case 31: return launch_moving_##tn##_d3_m1(p, seg, rpl, s);                          \
+    case 32: return launch_moving_##tn##_d3_m2(p, seg, rpl, s);                          \
+    case 33: return launch_moving_##tn##_d3_m3(p, seg, rpl, s);                          \
+    case 34: return launch_moving_##tn##_d3_m4(p, seg, rpl, s);                          \
+  }                                                                                      \
+  return hipErrorInvalidValue;
+
+inline hipError_t launch_moving(int d, int m, const MParams<double>& p, int seg, int rpl, hipStream_t s) {
+  CWENO_MOVE_CASES(f64)
+}
+inline hipError_t launch_moving(int d, int m, const MParams<float>& p, int seg, int rpl, hipStream_t s) {
+  CWENO_MOVE_CASES(f32)
+}
+#undef CWENO_MOVE_CASES
+
+}  // namespace cweno

@@ -1,0 +1,792 @@
+// CWENO reconstruction on a moving mesh (gfx950): the per-cell operators of
+// Sec. 2.1 are not read from memory but rebuilt inside the kernel from this
+// call's vertex positions, for the mesh's fixed connectivity and stencils.
+// On a moving (ALE) mesh the reconstruction matrices change with the geometry
+// at every step (Sec. 2.1), so storing them buys nothing; this trades the
+// operator stream for arithmetic.
+//
+// Work mapping.  A segment of SEG lanes (32 or 64) owns one cell.  Lane t of
+// the segment owns rows t, t + SEG, ... (RPL rows) of the cell's least-squares
+// matrix A' (row k: stencil cell k+1).  Per cell:
+//   1. every lane unwraps the cell's vertices (minimum image around vertex 0)
+//      and inverts its reference map x = X0 + J xi;
+//   2. each row lane places its stencil cell in that frame (translated by the
+//      minimum-image offset of the barycentres) and integrates psi_1 .. psi_NL
+//      over it with the Grundmann-Moller rule exact to degree M (eq.
+//      xietaTransf: every integral in the reference coordinates of the cell);
+//   3. columns are scaled to unit 2-norm and reduced by Householder
+//      reflections; the sums over the segment are butterflies (DPP within
+//      rows of 16 lanes, a swizzle across rows, lane reads across the halves
+//      of the wave).  Each reflector stays in the entries it eliminated;
+//   4. one lane per sector evaluates the linear basis functions at the sector
+//      cells' barycentres (the averages of a linear function), checks the
+//      2-norm condition number (above 1e10 the sector is dropped) and inverts
+//      the d x d system (eq. CWENO:Ps);
+//   5. per block of VB variables, the differences dQ of the row cells are
+//      reflected, R and Q^T dQ go to LDS, and one lane per variable solves
+//      R x = Q^T dQ, undoes the column scaling (P_opt, eq. CWENO:Popt with
+//      p_0 = Q_i), and forms the sector polynomials, P_0, the indicators, the
+//      nonlinear weights and the blend (eqs. CWENO:P0, weights, CWENO:Prec).
+// Everything is FP64; the averages and coefficients may be FP32 (converted on
+// load and on store; coefficient 0 is the cell's own average, bit for bit).
+//
+// A singular reference map ORs 1 into *fault, a zero column or a rank-
+// deficient R (a diagonal entry at or below 1e-12 of the largest) ORs 2; the
+// outputs of such a cell are not meaningful.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "reconstruct_kernel.hpp"
+
+namespace cweno {
+
+constexpr int kMoveVB = 4;         // variables reflected together
+constexpr int kMoveThreads = 256;  // four waves per block
+
+template <typename T>
+struct MParams {
+  const double* V;        // [n_vertices][D] positions for this call
+  const int32_t* C;       // [nc][D+1] vertex ids of each cell
+  const int32_t* S0;      // [nc][n_e] central stencil, the cell first
+  const int32_t* SS;      // [nc][D+1][D+1] sector stencils, the cell first; first entry < 0: not filled
+  const double* rule;     // [nq][D+2] quadrature: barycentric coordinates, then the weight (weights sum 1)
+  const T* q;             // [nv][nc]
+  T* out;                 // [nv][NB][nc]
+  T* sig;                 // optional [nv][D+2][nc]
+  T* om;                  // optional [nv][D+2][nc]
+  int* fault;             // optional
+  double box[3];          // period per axis, 0 = none
+  double lam[5];          // linear weights lambda_0 .. lambda_{D+1}
+  double eps;
+  int64_t nc;
+  int n_e, nq, nv, r, sigma0_popt, linear_w;
+};
+
+// f(std::integral_constant<int, I>) for I = 0 .. N-1, each call with a
+// compile-time index (register arrays are then indexed statically even where
+// the loop body is too large for the unroller).
+template <int I, int N>
+struct StaticFor {
+  template <typename F>
+  __device__ __forceinline__ static void run(F& f) {
+    f(std::integral_constant<int, I>{});
+    StaticFor<I + 1, N>::run(f);
+  }
+};
+template <int N>
+struct StaticFor<N, N> {
+  template <typename F>
+  __device__ __forceinline__ static void run(F&) {}
+};
+
+// ---------------------------------------------------------------- lane exchange
+
+__device__ __forceinline__ uint32_t lo32(double x) { return (uint32_t)__builtin_bit_cast(uint64_t, x); }
+__device__ __forceinline__ uint32_t hi32(double x) { return (uint32_t)(__builtin_bit_cast(uint64_t, x) >> 32); }
+__device__ __forceinline__ double mkd(uint32_t lo, uint32_t hi) {
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)lo);
+}
+
+// DPP move of a double: every lane reads the lane selected by CTRL (a
+// permutation within each row of 16 lanes, so no lane is out of range).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  return mkd((uint32_t)__builtin_amdgcn_mov_dpp((int)lo32(x), CTRL, 0xF, 0xF, false),
+             (uint32_t)__builtin_amdgcn_mov_dpp((int)hi32(x), CTRL, 0xF, 0xF, false));
+}
+// Swizzle (bit-mask mode) of a double within each group of 32 lanes.
+template <int PAT>
+__device__ __forceinline__ double swz_d(double x) {
+  return mkd((uint32_t)__builtin_amdgcn_ds_swizzle((int)lo32(x), PAT),
+             (uint32_t)__builtin_amdgcn_ds_swizzle((int)hi32(x), PAT));
+}
+// Value of lane l (wave-uniform l).
+__device__ __forceinline__ double rdl_d(double x, int l) {
+  return mkd((uint32_t)__builtin_amdgcn_readlane((int)lo32(x), l),
+             (uint32_t)__builtin_amdgcn_readlane((int)hi32(x), l));
+}
+
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane 7-l within each 8
+constexpr int kDppMirror = 0x140;     // lane 15-l within each 16
+constexpr int kSwzXor16 = 0x401F;     // and 0x1f, xor 0x10
+
+// x[c] for first <= c < last := the sum of x[c] over the lanes of the segment,
+// the same bits in every lane (each stage pairs every lane with one lane of
+// the other half of its group, whose partial sum it then shares).  Every lane
+// of the wave must be active.
+template <int SEG, int N>
+__device__ __forceinline__ void seg_sum(double (&x)[N], int first = 0, int last = N) {
+  static_assert(SEG == 32 || SEG == 64, "segment of 32 or 64 lanes");
+#pragma unroll
+  for (int c = 0; c < N; ++c)
+    if (c >= first && c < last) x[c] += dpp_d<kDppXor1>(x[c]);
+#pragma unroll
+  for (int c = 0; c < N; ++c)
+    if (c >= first && c < last) x[c] += dpp_d<kDppXor2>(x[c]);
+#pragma unroll
+  for (int c = 0; c < N; ++c)
+    if (c >= first && c < last) x[c] += dpp_d<kDppHalfMirror>(x[c]);
+#pragma unroll
+  for (int c = 0; c < N; ++c)
+    if (c >= first && c < last) x[c] += dpp_d<kDppMirror>(x[c]);
+#pragma unroll
+  for (int c = 0; c < N; ++c)
+    if (c >= first && c < last) x[c] += swz_d<kSwzXor16>(x[c]);
+  if constexpr (SEG == 64) {
+#pragma unroll
+    for (int c = 0; c < N; ++c)
+      if (c >= first && c < last) x[c] = rdl_d(x[c], 0) + rdl_d(x[c], 32);
+  }
+}
+
+// Value of x in lane `src` of this lane's segment (src uniform).
+template <int SEG>
+__device__ __forceinline__ double seg_bcast(double x, int src, int seg) {
+  if constexpr (SEG == 64) {
+    return rdl_d(x, src);
+  } else {
+    const double a = rdl_d(x, src), b = rdl_d(x, src + 32);
+    return seg ? b : a;
+  }
+}
+
+// ---------------------------------------------------------------- small dense algebra
+
+__device__ __forceinline__ double min_image_d(double d, double L) {
+  return L != 0.0 ? d - L * floor(d / L + 0.5) : d;
+}
+
+// Inverse of a small dense matrix (Gauss-Jordan, partial pivoting); false if
+// a pivot vanishes.
+template <int N>
+__device__ __forceinline__ bool invert_small(const double (&A)[N][N], double (&Ai)[N][N]) {
+  double W[N][2 * N];
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = 0; c < 2 * N; ++c) W[r][c] = c < N ? A[r][c] : (c - N == r ? 1.0 : 0.0);
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    // pivot row brought to position c by conditional swaps (no dynamic indexing)
+#pragma unroll
+    for (int r = c + 1; r < N; ++r) {
+      const bool sw = fabs(W[r][c]) > fabs(W[c][c]);
+#pragma unroll
+      for (int k = 0; k < 2 * N; ++k) {
+        const double a = W[c][k], b = W[r][k];
+        W[c][k] = sw ? b : a;
+        W[r][k] = sw ? a : b;
+      }
+    }
+    const double pv = W[c][c];
+    ok = ok && pv != 0.0;
+    const double ip = 1.0 / pv;
+#pragma unroll
+    for (int k = 0; k < 2 * N; ++k) W[c][k] *= ip;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      if (r == c) continue;
+      const double f = W[r][c];
+#pragma unroll
+      for (int k = 0; k < 2 * N; ++k) W[r][k] = fma(-f, W[c][k], W[r][k]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = 0; c < N; ++c) Ai[r][c] = W[r][N + c];
+  return ok;
+}
+
+// 2-norm condition number of a small square matrix: square root of the ratio
+// of the extreme eigenvalues of B^T B, found by cyclic Jacobi rotations.
+template <int N>
+__device__ __forceinline__ double cond2_small(const double (&B)[N][N]) {
+  double S[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(B[k][i], B[k][j], s);
+      S[i][j] = s;
+    }
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i + 1; j < N; ++j) off = fma(S[i][j], S[i][j], off);
+    if (off < 1e-300) break;
+#pragma unroll
+    for (int p = 0; p < N; ++p)
+#pragma unroll
+      for (int q = p + 1; q < N; ++q) {
+        const double apq = S[p][q];
+        const double th = (S[q][q] - S[p][p]) / (2.0 * (apq != 0.0 ? apq : 1.0));
+        double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
+        t = apq != 0.0 ? t : 0.0;
+        const double c = 1.0 / sqrt(fma(t, t, 1.0)), s = t * c;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const double a = S[k][p], b = S[k][q];
+          S[k][p] = c * a - s * b;
+          S[k][q] = s * a + c * b;
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const double a = S[p][k], b = S[q][k];
+          S[p][k] = c * a - s * b;
+          S[q][k] = s * a + c * b;
+        }
+      }
+  }
+  double lo = S[0][0], hi = S[0][0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) {
+    lo = fmin(lo, S[i][i]);
+    hi = fmax(hi, S[i][i]);
+  }
+  return lo > 0.0 ? sqrt(hi / lo) : INFINITY;
+}
+
+// ---------------------------------------------------------------- basis
+
+// Homogenised Jacobi values H[0..n] with parameter alpha at (u, v):
+// H_n = v^n P_n^(alpha,0)(u/v) by the three-term recurrence multiplied through
+// by powers of v; n and alpha are compile-time constants after unrolling.
+template <int NMAX>
+__device__ __forceinline__ void jac_h(int n, int alpha, double u, double v, double (&H)[NMAX + 1]) {
+  H[0] = 1.0;
+  if (n >= 1) H[1] = ((alpha + 2) * u + alpha * v) / 2.0;
+  const double v2 = v * v;
+#pragma unroll
+  for (int k = 1; k < NMAX; ++k) {
+    if (k >= n) break;
+    const double a1 = 2.0 * (k + 1) * (k + alpha + 1) * (2.0 * k + alpha);
+    const double c2 = (2.0 * k + alpha + 1) * alpha * alpha / a1;
+    const double c3 = (2.0 * k + alpha) * (2.0 * k + alpha + 1) * (2.0 * k + alpha + 2) / a1;
+    const double c4 = 2.0 * k * (k + alpha) * (2.0 * k + alpha + 2) / a1;
+    H[k + 1] = (c3 * u + c2 * v) * H[k] - c4 * v2 * H[k - 1];
+  }
+}
+
+// Position of psi_{p,q,r} in the library's order of the basis: total degree
+// n = p + q + r, then p descending, then q descending (r = 0 in 2-D).
+__host__ __device__ constexpr int basis_index(int D, int p, int q, int r) {
+  const int n = p + q + r;
+  int l = n == 0 ? 0 : nbasis_c(n - 1, D);
+  if (D == 2) return l + (n - p);
+  for (int pp = n; pp > p; --pp) l += n - pp + 1;
+  return l + (n - p - q);
+}
+
+// acc[l - 1] += w * psi_l(xi) for l = 1 .. NB-1: the orthonormal collapsed-
+// coordinate (Dubiner) basis, (1/|T_E|) int psi^2 = 1, evaluated factor by
+// factor so that no table of all values is held.
+template <int D, int M>
+__device__ __forceinline__ void basis_accumulate(const double (&xi)[D], double w, double (&acc)[nbasis_c(M, D) - 1]) {
+  if constexpr (D == 2) {
+    const double x = xi[0], y = xi[1];
+    double F[M + 1];
+    jac_h<M>(M, 0, 2.0 * x + y - 1.0, 1.0 - y, F);
+#pragma unroll
+    for (int p = 0; p <= M; ++p) {
+      double G[M + 1];
+      jac_h<M>(M - p, 2 * p + 1, 2.0 * y - 1.0, 1.0, G);
+      const double wf = w * F[p];
+#pragma unroll
+      for (int q = 0; q <= M; ++q) {
+        if (p + q == 0 || p + q > M) continue;
+        const double nrm = __builtin_sqrt((2.0 * p + 1.0) * (p + q + 1.0));
+        const int l = basis_index(2, p, q, 0);
+        acc[l - 1] = fma(wf * nrm, G[q], acc[l - 1]);
+      }
+    }
+  } else {
+    const double x = xi[0], y = xi[1], z = xi[2];
+    double F[M + 1];
+    jac_h<M>(M, 0, 2.0 * x + y + z - 1.0, 1.0 - y - z, F);
+#pragma unroll
+    for (int p = 0; p <= M; ++p) {
+      double H[M + 1];
+      jac_h<M>(M - p, 2 * p + 1, 2.0 * y + z - 1.0, 1.0 - z, H);
+#pragma unroll
+      for (int q = 0; q <= M; ++q) {
+        if (p + q > M) continue;
+        double K[M + 1];
+        jac_h<M>(M - p - q, 2 * p + 2 * q + 2, 2.0 * z - 1.0, 1.0, K);
+        const double wfh = w * F[p] * H[q];
+#pragma unroll
+        for (int r = 0; r <= M; ++r) {
+          if (p + q + r == 0 || p + q + r > M) continue;
+          const double nrm = __builtin_sqrt((2.0 * p + 1.0) * (2.0 * p + 2.0 * q + 2.0) *
+                                            (2.0 * p + 2.0 * q + 2.0 * r + 3.0) / 6.0);
+          const int l = basis_index(3, p, q, r);
+          acc[l - 1] = fma(wfh * nrm, K[r], acc[l - 1]);
+        }
+      }
+    }
+  }
+}
+
+// The d linear basis functions psi_1 .. psi_d at xi.
+template <int D>
+__device__ __forceinline__ void linear_basis(const double (&xi)[D], double (&out)[D]) {
+  double acc[D];
+#pragma unroll
+  for (int l = 0; l < D; ++l) acc[l] = 0.0;
+  basis_accumulate<D, 1>(xi, 1.0, acc);
+#pragma unroll
+  for (int l = 0; l < D; ++l) out[l] = acc[l];
+}
+
+// ---------------------------------------------------------------- geometry
+
+// Vertices of cell c, each moved to its minimum image around vertex 0.
+template <int D, typename T>
+__device__ __forceinline__ void cell_vertices(const MParams<T>& p, int64_t c, double (&X)[D + 1][D]) {
+  int32_t id[D + 1];
+#pragma unroll
+  for (int v = 0; v <= D; ++v) id[v] = p.C[c * (D + 1) + v];
+#pragma unroll
+  for (int v = 0; v <= D; ++v)
+#pragma unroll
+    for (int a = 0; a < D; ++a) X[v][a] = p.V[(int64_t)id[v] * D + a];
+#pragma unroll
+  for (int v = 1; v <= D; ++v)
+#pragma unroll
+    for (int a = 0; a < D; ++a) X[v][a] = X[0][a] + min_image_d(X[v][a] - X[0][a], p.box[a]);
+}
+
+template <int D>
+__device__ __forceinline__ void barycentre(const double (&X)[D + 1][D], double (&c)[D]) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    double s = X[0][a];
+#pragma unroll
+    for (int v = 1; v <= D; ++v) s = s + X[v][a];
+    c[a] = s / (double)(D + 1);
+  }
+}
+
+// ---------------------------------------------------------------- kernel
+
+template <int D, int M, int SEG, int RPL, typename T>
+__global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
+  constexpr int NB = nbasis_c(M, D);
+  constexpr int NL = NB - 1;
+  constexpr int NS = D + 1;
+  constexpr int VB = kMoveVB;
+  constexpr int CPW = 64 / SEG;                          // cells per wave
+  constexpr int CPB = (kMoveThreads / 64) * CPW;         // cells per block
+  constexpr int CH = 8;                                  // column sums in flight
+  static_assert(SEG * RPL > NL, "a segment must hold at least NL + 1 rows");
+  // per-cell LDS record (doubles): R (rows, upper part), Q^T dQ, column scales,
+  // diagonal of R, reflector factors, sector inverses
+  constexpr int OR = 0, OY = OR + NL * NL, OSC = OY + VB * NL, ORD = OSC + NL, OTAU = ORD + NL,
+                OBI = OTAU + NL, OSZ = OBI + NS * D * D;
+  __shared__ double lds[CPB * OSZ];
+  __shared__ int32_t ljs[CPB * NS * D];
+
+  const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+  const int seg = lane / SEG, sl = lane % SEG;
+  const int cs = wave * CPW + seg;
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * CPB + cs;
+  const bool valid = i < p.nc;
+  const int64_t ic = valid ? i : p.nc - 1;
+  double* const L = lds + cs * OSZ;
+  int32_t* const LJ = ljs + cs * NS * D;
+  const int NE1 = p.n_e - 1;
+  const int64_t nc = p.nc;
+  int fault = 0;
+
+  // 1. the cell's own frame
+  double X0[D], Jinv[D][D], ci[D];
+  {
+    double X[NS][D];
+    cell_vertices<D>(p, ic, X);
+    double J[D][D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      X0[r] = X[0][r];
+#pragma unroll
+      for (int c = 0; c < D; ++c) J[r][c] = X[c + 1][r] - X[0][r];
+    }
+    if (!invert_small<D>(J, Jinv)) fault |= 1;
+    barycentre<D>(X, ci);
+  }
+
+  // 2. rows of A': averages of psi_1 .. psi_NL over the stencil cells
+  int row[RPL];
+  bool rv[RPL];
+  int32_t jr[RPL];
+  double A[RPL][NL];
+  auto row_t = [&](auto tc) {
+    constexpr int t = decltype(tc)::value;
+    row[t] = sl + SEG * t;
+    rv[t] = row[t] < NE1;
+    jr[t] = rv[t] ? p.S0[ic * p.n_e + row[t] + 1] : (int32_t)ic;
+    double a[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) a[l] = 0.0;
+    if (rv[t]) {
+      double X[NS][D], cj[D], sh[D], Y[NS][D];
+      cell_vertices<D>(p, jr[t], X);
+      barycentre<D>(X, cj);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const double dc = cj[a] - ci[a];
+        sh[a] = min_image_d(dc, p.box[a]) - dc;
+      }
+#pragma unroll
+      for (int v = 0; v < NS; ++v) {
+        double y[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) y[a] = X[v][a] + sh[a] - X0[a];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          double s = 0.0;
+#pragma unroll
+          for (int a = 0; a < D; ++a) s = fma(Jinv[r][a], y[a], s);
+          Y[v][r] = s;
+        }
+      }
+      for (int qq = 0; qq < p.nq; ++qq) {
+        const double* w = p.rule + qq * (D + 2);
+        double xi[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) xi[r] = 0.0;
+#pragma unroll
+        for (int v = 0; v < NS; ++v)
+#pragma unroll
+          for (int r = 0; r < D; ++r) xi[r] = fma(w[v], Y[v][r], xi[r]);
+        basis_accumulate<D, M>(xi, w[D + 1], a);
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < NL; ++l) A[t][l] = a[l];
+  };
+  StaticFor<0, RPL>::run(row_t);
+
+  // 3a. unit column norms
+  {
+    double cn[NL];
+#pragma unroll
+    for (int c = 0; c < NL; ++c) {
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) s = fma(A[t][c], A[t][c], s);
+      cn[c] = s;
+    }
+    seg_sum<SEG, NL>(cn, 0);
+#pragma unroll
+    for (int c = 0; c < NL; ++c) {
+      const double s = sqrt(cn[c]);
+      if (!(s > 0.0)) fault |= 2;
+      const double is = 1.0 / s;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) A[t][c] *= is;
+      if (sl == 0) L[OSC + c] = s;
+    }
+  }
+  // 3b. Householder QR; reflector k replaces column k from row k down (the
+  // steps and column chunks are expanded at compile time, so that A stays in
+  // registers however large the unrolled body)
+  auto qr_step = [&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    double x[RPL];
+    double nn[1] = {0.0};
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      x[t] = row[t] >= k ? A[t][k] : 0.0;
+      nn[0] = fma(x[t], x[t], nn[0]);
+    }
+    seg_sum<SEG, 1>(nn, 0);
+    const double nrm = sqrt(nn[0]);
+    const double akk = seg_bcast<SEG>(A[k / SEG][k], k % SEG, seg);
+    const double alpha = akk > 0.0 ? -nrm : nrm;
+    const double vn2 = 2.0 * nrm * (nrm + fabs(akk));   // |x - alpha e_k|^2
+    if (!(vn2 > 0.0)) fault |= 2;
+    const double tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+    double vk[RPL];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) vk[t] = row[t] == k ? akk - alpha : x[t];
+    // the columns right of k, in chunks of CH reduced together
+    auto chunk = [&](auto cc) {
+      constexpr int c0 = decltype(cc)::value * CH;
+      if constexpr (c0 + CH > k + 1) {
+      double dot[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int c = c0 + u < NL ? c0 + u : NL - 1;
+        double s = 0.0;
+        if (c0 + u > k && c0 + u < NL) {
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) s = fma(vk[t], A[t][c], s);
+        }
+        dot[u] = s;
+      }
+      seg_sum<SEG, CH>(dot, k + 1 - c0 > 0 ? k + 1 - c0 : 0, NL - c0 < CH ? NL - c0 : CH);
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int c = c0 + u < NL ? c0 + u : NL - 1;
+        if (c0 + u > k && c0 + u < NL) {
+          const double f = -tau * dot[u];
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) A[t][c] = fma(f, vk[t], A[t][c]);
+        }
+      }
+      }
+    };
+    StaticFor<0, (NL + CH - 1) / CH>::run(chunk);
+#pragma unroll
+    for (int t = 0; t < RPL; ++t)
+      if (row[t] >= k) A[t][k] = vk[t];
+    if (sl == 0) {
+      L[ORD + k] = alpha;
+      L[OTAU + k] = tau;
+    }
+  };
+  StaticFor<0, NL>::run(qr_step);
+  // rows of R above the diagonal
+#pragma unroll
+  for (int t = 0; t < RPL; ++t)
+#pragma unroll
+    for (int c = 0; c < NL; ++c)
+      if (row[t] < c) L[OR + row[t] * NL + c] = A[t][c];
+
+  // 4. sectors: lane s of the segment builds and inverts sector s
+  bool kept = false;
+  if (sl < NS) {
+    const int s = sl;
+    const int32_t* ss = p.SS + (ic * NS + s) * NS;
+    double Bi[D][D];
+#pragma unroll
+    for (int l = 0; l < D; ++l)
+#pragma unroll
+      for (int a = 0; a < D; ++a) Bi[l][a] = 0.0;
+    int32_t sj[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) sj[a] = (int32_t)ic;
+    if (ss[0] >= 0) {
+      double B[D][D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        sj[a] = ss[a + 1];
+        double X[NS][D], cj[D], y[D], xi[D];
+        cell_vertices<D>(p, sj[a], X);
+        barycentre<D>(X, cj);
+#pragma unroll
+        for (int b = 0; b < D; ++b) y[b] = ci[b] + min_image_d(cj[b] - ci[b], p.box[b]) - X0[b];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          double t = 0.0;
+#pragma unroll
+          for (int b = 0; b < D; ++b) t = fma(Jinv[r][b], y[b], t);
+          xi[r] = t;
+        }
+        linear_basis<D>(xi, B[a]);
+      }
+      double Binv[D][D];
+      if (cond2_small<D>(B) <= 1e10 && invert_small<D>(B, Binv)) {
+        kept = true;
+#pragma unroll
+        for (int l = 0; l < D; ++l)
+#pragma unroll
+          for (int a = 0; a < D; ++a) Bi[l][a] = Binv[l][a];
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < D; ++l)
+#pragma unroll
+      for (int a = 0; a < D; ++a) L[OBI + (s * D + l) * D + a] = Bi[l][a];
+#pragma unroll
+    for (int a = 0; a < D; ++a) LJ[s * D + a] = sj[a];
+  }
+  const unsigned kmask = (unsigned)(__ballot(kept) >> (seg * SEG)) & ((1u << NS) - 1u);
+  __syncthreads();
+
+  // linear weights of the cell: dropped sectors get 0, the rest renormalised
+  double lam[NS + 1];
+  {
+    double lsum = p.lam[0];
+    lam[0] = p.lam[0];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      lam[s + 1] = ((kmask >> s) & 1u) ? p.lam[s + 1] : 0.0;
+      lsum += lam[s + 1];
+    }
+#pragma unroll
+    for (int s = 0; s <= NS; ++s) lam[s] /= lsum;
+  }
+  const double inv_l0 = 1.0 / lam[0];
+
+  // 5. variable blocks
+  for (int v0 = 0; v0 < p.nv; v0 += VB) {
+    const int nvb = min(VB, p.nv - v0);
+    double dq[RPL][VB];
+#pragma unroll
+    for (int v = 0; v < VB; ++v) {
+      const bool act = v < nvb;
+      const T* qv = p.q + (int64_t)(act ? v0 + v : v0) * nc;
+      const double qi = (double)qv[ic];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) dq[t][v] = (act && rv[t]) ? (double)qv[jr[t]] - qi : 0.0;
+    }
+    auto reflect = [&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const double tau = L[OTAU + k];
+      double vk[RPL];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) vk[t] = row[t] >= k ? A[t][k] : 0.0;
+      double dd[VB];
+#pragma unroll
+      for (int v = 0; v < VB; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) s = fma(vk[t], dq[t][v], s);
+        dd[v] = s;
+      }
+      seg_sum<SEG, VB>(dd, 0);
+#pragma unroll
+      for (int v = 0; v < VB; ++v) {
+        const double f = -tau * dd[v];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) dq[t][v] = fma(f, vk[t], dq[t][v]);
+      }
+    };
+    StaticFor<0, NL>::run(reflect);
+#pragma unroll
+    for (int t = 0; t < RPL; ++t)
+      if (row[t] < NL) {
+#pragma unroll
+        for (int v = 0; v < VB; ++v) L[OY + v * NL + row[t]] = dq[t][v];
+      }
+    __syncthreads();
+
+    if (valid && sl < nvb) {
+      const int v = v0 + sl;
+      const T* qv = p.q + (int64_t)v * nc;
+      const T qiT = qv[i];
+      const double qi = (double)qiT;
+      // P_opt: back substitution in place of Q^T dQ, then the column scales
+      double* const y = L + OY + sl * NL;
+#pragma unroll 1
+      for (int k = NL - 1; k >= 0; --k) {
+        double s = y[k];
+        for (int c = k + 1; c < NL; ++c) s = fma(-L[OR + k * NL + c], y[c], s);
+        y[k] = s / L[ORD + k];
+      }
+      if (v0 == 0) {
+        double rmax = 0.0;
+        for (int k = 0; k < NL; ++k) rmax = fmax(rmax, fabs(L[ORD + k]));
+        for (int k = 0; k < NL; ++k)
+          if (!(fabs(L[ORD + k]) > 1e-12 * rmax)) fault |= 2;
+      }
+      double po[NL];
+#pragma unroll
+      for (int l = 0; l < NL; ++l) po[l] = y[l] / L[OSC + l];
+      // sectorial P1 polynomials
+      double ps[NS][D];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        double dqs[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) dqs[a] = (double)qv[LJ[s * D + a]] - qi;
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+          double x = 0.0;
+#pragma unroll
+          for (int a = 0; a < D; ++a) x = fma(L[OBI + (s * D + l) * D + a], dqs[a], x);
+          ps[s][l] = x;
+        }
+      }
+      // P_0 = (P_opt - sum_s lambda_s P_s) / lambda_0, kept as u = lambda_0 P_0
+      const bool s_popt = p.sigma0_popt;
+      double u[D];
+#pragma unroll
+      for (int l = 0; l < D; ++l) {
+        double x = po[l];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) x = fma(-lam[s + 1], ps[s][l], x);
+        u[l] = x;
+        po[l] = s_popt ? po[l] : x;
+      }
+      double sg[NS + 1];
+      sg[0] = quad_form<D, M, double>(po) * (s_popt ? 1.0 : inv_l0 * inv_l0);
+#pragma unroll
+      for (int l = 0; l < D; ++l) po[l] = u[l];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        double x = 0.0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+          double y = 0.0;
+#pragma unroll
+          for (int m = l + 1; m < D; ++m) y = fma(SigmaTable<D, M>::v[l * NL + m], ps[s][m], y);
+          x = fma(ps[s][l], fma(2.0, y, SigmaTable<D, M>::v[l * NL + l] * ps[s][l]), x);
+        }
+        sg[s + 1] = x;
+      }
+      double om[NS + 1];
+      if (p.linear_w) {
+#pragma unroll
+        for (int s = 0; s <= NS; ++s) om[s] = lam[s];
+      } else {
+        double ms[NS + 1];
+#pragma unroll
+        for (int s = 0; s <= NS; ++s) ms[s] = sg[s] + p.eps;
+        double mmin = ms[0];
+#pragma unroll
+        for (int s = 1; s <= NS; ++s)
+          if (lam[s] > 0.0) mmin = fmin(mmin, ms[s]);
+#pragma unroll
+        for (int s = 0; s <= NS; ++s) om[s] = mmin / ms[s];
+        powi<NS + 1, double>(om, p.r);
+        double tot = 0.0;
+#pragma unroll
+        for (int s = 0; s <= NS; ++s) {
+          om[s] *= lam[s];
+          tot += om[s];
+        }
+#pragma unroll
+        for (int s = 0; s <= NS; ++s) om[s] /= tot;
+      }
+      T* o = p.out + (int64_t)v * NB * nc + i;
+      o[0] = qiT;
+      const double c0 = om[0] * inv_l0;
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        double x = c0 * po[l];
+        if (l < D) {
+#pragma unroll
+          for (int s = 0; s < NS; ++s) x = fma(om[s + 1], ps[s][l < D ? l : 0], x);
+        }
+        o[(int64_t)(l + 1) * nc] = (T)x;
+      }
+      if (p.sig) {
+        T* g = p.sig + (int64_t)v * (NS + 1) * nc + i;
+#pragma unroll
+        for (int s = 0; s <= NS; ++s) g[(int64_t)s * nc] = (T)sg[s];
+      }
+      if (p.om) {
+        T* g = p.om + (int64_t)v * (NS + 1) * nc + i;
+#pragma unroll
+        for (int s = 0; s <= NS; ++s) g[(int64_t)s * nc] = (T)om[s];
+      }
+    }
+    __syncthreads();
+  }
+  if (fault && valid && p.fault) atomicOr(p.fault, fault);
+}
+
+}  // namespace cweno

@@ -1,0 +1,48 @@
+// Moving-mesh kernels for one (precision, dimension, degree), selected at
+// compile time by CWENO_TN (f64 | f32), CWENO_D and CWENO_M; the build compiles
+// this file once per combination.
+#include "moving.hpp"
+
+#if !defined(CWENO_TN) || !defined(CWENO_D) || !defined(CWENO_M)
+#error "compile with -DCWENO_TN=f64|f32 -DCWENO_D=2|3 -DCWENO_M=1..4"
+#endif
+
+#define CWENO_CAT4(a, b, c, d) a##b##c##d
+#define CWENO_MOVE_NAME(tn, d, m) CWENO_CAT4(launch_moving_, tn, _d##d, _m##m)
+#define CWENO_MOVE_FN(tn, d, m) CWENO_MOVE_NAME(tn, d, m)
+#define f64 1
+#define f32 2
+#if CWENO_TN == 1
+typedef double real_t;
+#else
+typedef float real_t;
+#endif
+#undef f64
+#undef f32
+
+namespace cweno {
+namespace {
+
+template <int SEG, int RPL>
+hipError_t launch_shape(const MParams<real_t>& p, hipStream_t s) {
+  if constexpr (move_shape_ok(CWENO_D, CWENO_M, SEG, RPL)) {
+    constexpr int cpb = (kMoveThreads / 64) * (64 / SEG);
+    const int64_t blocks = (p.nc + cpb - 1) / cpb;
+    hipLaunchKernelGGL((moving_kernel<CWENO_D, CWENO_M, SEG, RPL, real_t>), dim3((unsigned)blocks),
+                       dim3(kMoveThreads), 0, s, p);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t CWENO_MOVE_FN(CWENO_TN, CWENO_D, CWENO_M)(const MParams<real_t>& p, int seg, int rpl, hipStream_t s) {
+  if (seg == 32 && rpl == 1) return launch_shape<32, 1>(p, s);
+  if (seg == 64 && rpl == 1) return launch_shape<64, 1>(p, s);
+  if (seg == 64 && rpl == 2) return launch_shape<64, 2>(p, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace cweno

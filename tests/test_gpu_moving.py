@@ -1,0 +1,201 @@
+"""GPU parity of the moving-mesh path (operators rebuilt from the vertices on
+every call) against the oracle with the same fixed stencils on the moved
+vertices.
+
+Bars as for the stored-operator path: FP64 data-scaled coefficient error
+<= 1e-12, indicators to 1e-9 relative, weights to 1e-9 absolute; FP32
+averages and coefficients (FP64 arithmetic inside) to 2e-6; coefficient 0 is
+a bitwise copy of the input.  Every case uses a cell count that leaves the
+last workgroup partly empty, and variable counts that leave the last block
+of reflected variables partly empty.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from gpu_common import data_scaled_error, run_library, torch_cuda
+from oracle import CwenoOracle, Options
+from synthetic import kuhn_tet_mesh, moved_vertices, tri_mesh
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-12, 2e-6
+
+
+def _fields(m, nv, seed):
+    rng = np.random.default_rng(seed)
+    c = m.vertices[m.cells].mean(axis=1)
+    smooth = np.stack([np.sin(2 * np.pi * (c[:, 0] + 0.1 * v)) * np.cos(2 * np.pi * c[:, 1]) for v in range(nv)])
+    jump = (np.linalg.norm(c - 0.5, axis=1) < 0.3).astype(float)
+    return smooth + 2.0 * jump[None, :] + 0.05 * rng.normal(size=(nv, m.n_cells))
+
+
+def _run_moving(torch, lm, V, Q, dtype, fault=None):
+    dev = torch.device("cuda:0")
+    q = torch.tensor(Q, dtype=dtype, device=dev)
+    vt = torch.tensor(V, dtype=torch.float64, device=dev)
+    nv, d = Q.shape[0], lm.dim
+    out = torch.full((nv, lm.n_basis, lm.n_cells), float("nan"), dtype=dtype, device=dev)
+    sig = torch.full((nv, d + 2, lm.n_cells), float("nan"), dtype=dtype, device=dev)
+    om = torch.full((nv, d + 2, lm.n_cells), float("nan"), dtype=dtype, device=dev)
+    lm.reconstruct_moving(vt, q, out=out, sigma=sig, omega=om, fault=fault)
+    torch.cuda.synchronize()
+    return dict(coeffs=out.cpu().numpy().astype(np.float64), sigma=sig.cpu().numpy().astype(np.float64),
+                omega=om.cpu().numpy().astype(np.float64), q=q.cpu().numpy())
+
+
+def _compare(res, ref, Q, st, tol, diag=True):
+    err = data_scaled_error(res["coeffs"], ref["coeffs"], Q, st)
+    if diag:
+        scale2 = (np.abs(Q[:, st]).max(axis=2) ** 2)[:, None, :]
+        assert np.all(np.abs(res["sigma"] - ref["sigma"]) <= 1e-9 * np.abs(ref["sigma"]) + 1e-20 * scale2)
+        assert np.abs(res["omega"] - ref["omega"]).max() <= 1e-9
+    return err
+
+
+CASES = {
+    # name: (mesh factory, degree, variables, stencil factor)
+    "tri11_M1_nv3": (lambda: tri_mesh(11, 0.15, 501), 1, 3, 0.0),
+    "tri11_M2_nv5": (lambda: tri_mesh(11, 0.15, 502), 2, 5, 0.0),
+    "tri12_M3_nv9": (lambda: tri_mesh(12, 0.15, 503), 3, 9, 0.0),
+    "tri12_M4_nv2": (lambda: tri_mesh(12, 0.15, 504), 4, 2, 0.0),
+    "tri12_M3_f3.5_nv4": (lambda: tri_mesh(12, 0.15, 505), 3, 4, 3.5),        # 34 stencil rows: 64-lane segments
+    "kuhn4_M1_nv5": (lambda: kuhn_tet_mesh(4, 0.1, 506), 1, 5, 0.0),
+    "kuhn4_M2_nv5": (lambda: kuhn_tet_mesh(4, 0.1, 507), 2, 5, 0.0),
+    "kuhn5_M3_nv5": (lambda: kuhn_tet_mesh(5, 0.1, 508), 3, 5, 0.0),
+    "kuhn5_M4_nv3": (lambda: kuhn_tet_mesh(5, 0.1, 509), 4, 3, 0.0),          # 104 stencil rows: two per lane
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_moved_mesh_against_oracle(case):
+    torch = torch_cuda()
+    import paper_1612_09335_amd as C
+    mk, M, nv, factor = CASES[case]
+    m = mk()
+    print(f"[gpu moving] {case}: {m.n_cells} cells", flush=True)
+    lm = C.Mesh(m.vertices, m.cells, M, periodic=m.box, stencil_factor=factor, ops="none", moving=True)
+    V = moved_vertices(m, 0.3, 0.15)
+    Q = _fields(dataclasses.replace(m, vertices=V), nv, 510)
+    t = lm.tables()
+    o = CwenoOracle(V, m.cells, m.box, Options(degree=M, stencil_factor=factor),
+                    stencils=(t["stencil"], t["sectors"]))
+    rng = np.random.default_rng(511)
+    idx = np.unique(np.concatenate([rng.choice(m.n_cells, 24, replace=False), [0, m.n_cells - 1]]))
+    ref = o.reconstruct(Q, cells=idx)
+    st = t["stencil"][idx]
+    fault = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    r64 = _run_moving(torch, lm, V, Q, torch.float64, fault)
+    assert int(fault.item()) == 0
+    assert np.array_equal(r64["coeffs"][:, 0, :].view(np.int64), Q.view(np.int64))
+    assert np.isfinite(r64["coeffs"]).all()
+    sub = {k: r64[k][:, :, idx] for k in ("coeffs", "sigma", "omega")}
+    err = _compare(sub, ref, Q, st, TOL64)
+    print(f"[gpu moving]   f64 data-scaled error {err:.3e}", flush=True)
+    assert err <= TOL64
+    r32 = _run_moving(torch, lm, V, Q, torch.float32)
+    assert np.array_equal(r32["coeffs"][:, 0, :], Q.astype(np.float32).astype(np.float64))
+    err32 = data_scaled_error(r32["coeffs"][:, :, idx], ref["coeffs"], Q, st)
+    print(f"[gpu moving]   f32 data-scaled error {err32:.3e}", flush=True)
+    assert err32 <= TOL32
+    # deterministic
+    again = _run_moving(torch, lm, V, Q, torch.float64)
+    assert np.array_equal(again["coeffs"], r64["coeffs"])
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_static_positions_match_stored_operators(d):
+    """At the creation positions the rebuilt operators equal the stored ones
+    (to rounding): the two paths agree to the FP64 bar, and with the oracle."""
+    torch = torch_cuda()
+    import paper_1612_09335_amd as C
+    m = tri_mesh(13, 0.15, 520) if d == 2 else kuhn_tet_mesh(5, 0.1, 521)
+    M = 3 if d == 2 else 2
+    Q = _fields(m, 5, 522)
+    lm = C.Mesh(m.vertices, m.cells, M, periodic=m.box, moving=True)
+    stored = run_library(torch, lm, Q, torch.float64)
+    moving = _run_moving(torch, lm, m.vertices, Q, torch.float64)
+    st = lm.tables()["stencil"]
+    err = _compare(moving, stored, Q, st, TOL64)
+    print(f"[gpu moving] d={d}: moving vs stored data-scaled error {err:.3e}", flush=True)
+    assert err <= TOL64
+    o = CwenoOracle(m.vertices, m.cells, m.box, Options(degree=M))
+    idx = np.arange(0, m.n_cells, 9)
+    ref = o.reconstruct(Q, cells=idx)
+    assert data_scaled_error(moving["coeffs"][:, :, idx], ref["coeffs"], Q, st[idx]) <= TOL64
+
+
+def test_whole_period_shift_and_repeated_steps():
+    """Vertices moved by whole periods give the same reconstruction; a
+    sequence of steps with different positions matches the oracle at each."""
+    torch = torch_cuda()
+    import paper_1612_09335_amd as C
+    m = tri_mesh(10, 0.15, 530)
+    lm = C.Mesh(m.vertices, m.cells, 2, periodic=m.box, ops="f32", moving=True)
+    t = lm.tables()
+    Q = _fields(m, 4, 531)
+    V = moved_vertices(m, 0.25, 0.3)
+    V2 = V.copy()
+    rng = np.random.default_rng(532)
+    pick = rng.choice(m.n_vertices, m.n_vertices // 3, replace=False)
+    V2[pick, 0] += 1.0
+    V2[pick[::2], 1] -= 1.0
+    a = _run_moving(torch, lm, V, Q, torch.float64)
+    b = _run_moving(torch, lm, V2, Q, torch.float64)
+    assert data_scaled_error(b["coeffs"], a["coeffs"], Q, t["stencil"]) <= TOL64
+    idx = np.arange(0, m.n_cells, 11)
+    for step, phase in enumerate((0.0, 0.05, 0.1)):
+        Vs = moved_vertices(m, 0.2, phase)
+        got = _run_moving(torch, lm, Vs, Q, torch.float64)
+        o = CwenoOracle(Vs, m.cells, m.box, Options(degree=2), stencils=(t["stencil"], t["sectors"]))
+        ref = o.reconstruct(Q, cells=idx)
+        assert data_scaled_error(got["coeffs"][:, :, idx], ref["coeffs"], Q, t["stencil"][idx]) <= TOL64, step
+
+
+def test_degenerate_cell_reports_fault():
+    """A cell whose moved vertices coincide has a singular reference map:
+    the fault word gets bit 1; cells whose stencils avoid it stay exact."""
+    torch = torch_cuda()
+    import paper_1612_09335_amd as C
+    m = tri_mesh(10, 0.15, 540)
+    lm = C.Mesh(m.vertices, m.cells, 2, periodic=m.box, ops="none", moving=True)
+    V = m.vertices.copy()
+    bad = 37
+    a, b = m.cells[bad][0], m.cells[bad][1]
+    V[b] = V[a]
+    Q = _fields(m, 2, 541)
+    fault = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    res = _run_moving(torch, lm, V, Q, torch.float64, fault)
+    assert int(fault.item()) & 1
+    t = lm.tables()
+    touched = {int(c) for c in range(m.n_cells)
+               if a in m.cells[c] or b in m.cells[c] or bad in t["stencil"][c] or bad in t["sectors"][c]}
+    ok = np.array([c for c in range(m.n_cells) if c not in touched])
+    o = CwenoOracle(V, m.cells, m.box, Options(degree=2), stencils=(t["stencil"], t["sectors"]))
+    idx = ok[::7]
+    ref = o.reconstruct(Q, cells=idx)
+    assert data_scaled_error(res["coeffs"][:, :, idx], ref["coeffs"], Q, t["stencil"][idx]) <= TOL64
+
+
+def test_moving_mesh_arguments():
+    torch = torch_cuda()
+    import paper_1612_09335_amd as C
+    m = tri_mesh(8, 0.15, 550)
+    lm = C.Mesh(m.vertices, m.cells, 2, periodic=m.box, ops="none", moving=True)
+    q = torch.zeros((3, lm.n_cells), dtype=torch.float64, device="cuda:0")
+    v = torch.tensor(m.vertices, device="cuda:0")
+    with pytest.raises(C.CwenoError):
+        lm.reconstruct(q)                                  # no stored operators
+    fixed = C.Mesh(m.vertices, m.cells, 2, periodic=m.box)
+    with pytest.raises(C.CwenoError):
+        fixed.reconstruct_moving(v, q)                     # not created as a moving mesh
+    with pytest.raises(C.CwenoError):
+        C.Mesh(m.vertices, m.cells, 2, periodic=m.box, moving=True, host_only=True)
+    out = lm.reconstruct_moving(v, q)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(out).item() == 0           # zero data: zero coefficients
+    lib = C.lib
+    st = lib.cweno_reconstruct_moving(lm._h, v.data_ptr(), 3, C.F64, q.data_ptr(), q.data_ptr(), None, None,
+                                      None, None)
+    assert st == -1 and b"overlap" in lib.cweno_last_error()
