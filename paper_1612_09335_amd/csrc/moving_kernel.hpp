@@ -19,9 +19,9 @@
 //      rows of 16 lanes, a swizzle across rows, lane reads across the halves
 //      of the wave).  Each reflector stays in the entries it eliminated;
 //   4. one lane per sector evaluates the linear basis functions at the sector
-//      cells' barycentres (the averages of a linear function), checks the
-//      2-norm condition number (above 1e10 the sector is dropped) and inverts
-//      the d x d system (eq. CWENO:Ps);
+//      cells' barycentres (the averages of a linear function), inverts the
+//      d x d system (eq. CWENO:Ps) and drops the sector if its 2-norm
+//      condition number, sigma_max(B) sigma_max(B^-1), exceeds 1e10;
 //   5. per block of VB variables, the differences dQ of the row cells are
 //      reflected, R and Q^T dQ go to LDS, and one lane per variable solves
 //      R x = Q^T dQ, undoes the column scaling (P_opt, eq. CWENO:Popt with
@@ -205,10 +205,12 @@ __device__ __forceinline__ bool invert_small(const double (&A)[N][N], double (&A
   return ok;
 }
 
-// 2-norm condition number of a small square matrix: square root of the ratio
-// of the extreme eigenvalues of B^T B, found by cyclic Jacobi rotations.
+// Largest eigenvalue of B^T B (the squared largest singular value of B) in
+// closed form: the larger root of the 2 x 2 characteristic polynomial, or the
+// trigonometric solution of the symmetric 3 x 3 one (for the largest root
+// neither loses relative accuracy).
 template <int N>
-__device__ __forceinline__ double cond2_small(const double (&B)[N][N]) {
+__device__ __forceinline__ double sigma_max_sq(const double (&B)[N][N]) {
   double S[N][N];
 #pragma unroll
   for (int i = 0; i < N; ++i)
@@ -219,43 +221,22 @@ __device__ __forceinline__ double cond2_small(const double (&B)[N][N]) {
       for (int k = 0; k < N; ++k) s = fma(B[k][i], B[k][j], s);
       S[i][j] = s;
     }
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    double off = 0.0;
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = i + 1; j < N; ++j) off = fma(S[i][j], S[i][j], off);
-    if (off < 1e-300) break;
-#pragma unroll
-    for (int p = 0; p < N; ++p)
-#pragma unroll
-      for (int q = p + 1; q < N; ++q) {
-        const double apq = S[p][q];
-        const double th = (S[q][q] - S[p][p]) / (2.0 * (apq != 0.0 ? apq : 1.0));
-        double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
-        t = apq != 0.0 ? t : 0.0;
-        const double c = 1.0 / sqrt(fma(t, t, 1.0)), s = t * c;
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-          const double a = S[k][p], b = S[k][q];
-          S[k][p] = c * a - s * b;
-          S[k][q] = s * a + c * b;
-        }
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-          const double a = S[p][k], b = S[q][k];
-          S[p][k] = c * a - s * b;
-          S[q][k] = s * a + c * b;
-        }
-      }
+  if constexpr (N == 2) {
+    const double h = 0.5 * (S[0][0] - S[1][1]);
+    return 0.5 * (S[0][0] + S[1][1]) + sqrt(fma(h, h, S[0][1] * S[0][1]));
+  } else {
+    static_assert(N == 3, "2 x 2 or 3 x 3");
+    const double p1 = S[0][1] * S[0][1] + S[0][2] * S[0][2] + S[1][2] * S[1][2];
+    const double q = (S[0][0] + S[1][1] + S[2][2]) / 3.0;
+    if (!(p1 > 0.0)) return fmax(S[0][0], fmax(S[1][1], S[2][2]));
+    const double a = S[0][0] - q, b = S[1][1] - q, c = S[2][2] - q;
+    const double p = sqrt((a * a + b * b + c * c + 2.0 * p1) / 6.0);
+    const double ip = 1.0 / p;
+    const double x = a * ip, y = b * ip, z = c * ip, u = S[0][1] * ip, v = S[0][2] * ip, w = S[1][2] * ip;
+    const double det = x * (y * z - w * w) - u * (u * z - w * v) + v * (u * w - y * v);
+    const double r = fmin(1.0, fmax(-1.0, 0.5 * det));
+    return q + 2.0 * p * cos(acos(r) / 3.0);
   }
-  double lo = S[0][0], hi = S[0][0];
-#pragma unroll
-  for (int i = 1; i < N; ++i) {
-    lo = fmin(lo, S[i][i]);
-    hi = fmax(hi, S[i][i]);
-  }
-  return lo > 0.0 ? sqrt(hi / lo) : INFINITY;
 }
 
 // ---------------------------------------------------------------- basis
@@ -389,11 +370,11 @@ __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
   constexpr int CPW = 64 / SEG;                          // cells per wave
   constexpr int CPB = (kMoveThreads / 64) * CPW;         // cells per block
   constexpr int CH = 8;                                  // column sums in flight
-  static_assert(SEG * RPL > NL, "a segment must hold at least NL + 1 rows");
-  // per-cell LDS record (doubles): R (rows, upper part), Q^T dQ, column scales,
-  // diagonal of R, reflector factors, sector inverses
-  constexpr int OR = 0, OY = OR + NL * NL, OSC = OY + VB * NL, ORD = OSC + NL, OTAU = ORD + NL,
-                OBI = OTAU + NL, OSZ = OBI + NS * D * D;
+  static_assert(NL < SEG, "the rows of R lie in the first row slot of the segment's lanes");
+  // per-cell LDS record (doubles): P_opt of a block of variables, column
+  // scales, diagonal of R, reflector factors, sector inverses
+  constexpr int OP = 0, OSC = OP + VB * NL, ORD = OSC + NL, OTAU = ORD + NL, OBI = OTAU + NL,
+                OSZ = OBI + NS * D * D;
   __shared__ double lds[CPB * OSZ];
   __shared__ int32_t ljs[CPB * NS * D];
 
@@ -557,12 +538,6 @@ __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
     }
   };
   StaticFor<0, NL>::run(qr_step);
-  // rows of R above the diagonal
-#pragma unroll
-  for (int t = 0; t < RPL; ++t)
-#pragma unroll
-    for (int c = 0; c < NL; ++c)
-      if (row[t] < c) L[OR + row[t] * NL + c] = A[t][c];
 
   // 4. sectors: lane s of the segment builds and inverts sector s
   bool kept = false;
@@ -596,8 +571,9 @@ __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
         }
         linear_basis<D>(xi, B[a]);
       }
+      // 2-norm condition number sigma_max(B) sigma_max(B^-1), kept up to 1e10
       double Binv[D][D];
-      if (cond2_small<D>(B) <= 1e10 && invert_small<D>(B, Binv)) {
+      if (invert_small<D>(B, Binv) && sqrt(sigma_max_sq<D>(B) * sigma_max_sq<D>(Binv)) <= 1e10) {
         kept = true;
 #pragma unroll
         for (int l = 0; l < D; ++l)
@@ -629,6 +605,15 @@ __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
     for (int s = 0; s <= NS; ++s) lam[s] /= lsum;
   }
   const double inv_l0 = 1.0 / lam[0];
+
+  if (sl == 0) {   // rank: every diagonal entry of R above 1e-12 of the largest
+    double rmax = 0.0;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) rmax = fmax(rmax, fabs(L[ORD + k]));
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+      if (!(fabs(L[ORD + k]) > 1e-12 * rmax)) fault |= 2;
+  }
 
   // 5. variable blocks
   for (int v0 = 0; v0 < p.nv; v0 += VB) {
@@ -665,36 +650,36 @@ __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
       }
     };
     StaticFor<0, NL>::run(reflect);
+    // back substitution R x = Q^T dQ over the row lanes: x_k is formed from
+    // the lane of row k, broadcast, and removed from the rows above it
+    auto back = [&](auto kc) {
+      constexpr int k = NL - 1 - decltype(kc)::value;
+      const double ik = 1.0 / L[ORD + k];
+      double xk[VB];
 #pragma unroll
-    for (int t = 0; t < RPL; ++t)
-      if (row[t] < NL) {
+      for (int v = 0; v < VB; ++v) xk[v] = seg_bcast<SEG>(dq[0][v], k, seg) * ik;
+      if (row[0] < k) {
+        const double rk = A[0][k];
 #pragma unroll
-        for (int v = 0; v < VB; ++v) L[OY + v * NL + row[t]] = dq[t][v];
+        for (int v = 0; v < VB; ++v) dq[0][v] = fma(-rk, xk[v], dq[0][v]);
       }
+    };
+    StaticFor<0, NL>::run(back);
+    // P_opt coefficient r of each variable (column scale undone), to LDS
+    if (row[0] < NL) {
+      const double f = 1.0 / (L[ORD + row[0]] * L[OSC + row[0]]);
+#pragma unroll
+      for (int v = 0; v < VB; ++v) L[OP + v * NL + row[0]] = dq[0][v] * f;
+    }
     __syncthreads();
-
     if (valid && sl < nvb) {
       const int v = v0 + sl;
       const T* qv = p.q + (int64_t)v * nc;
       const T qiT = qv[i];
       const double qi = (double)qiT;
-      // P_opt: back substitution in place of Q^T dQ, then the column scales
-      double* const y = L + OY + sl * NL;
-#pragma unroll 1
-      for (int k = NL - 1; k >= 0; --k) {
-        double s = y[k];
-        for (int c = k + 1; c < NL; ++c) s = fma(-L[OR + k * NL + c], y[c], s);
-        y[k] = s / L[ORD + k];
-      }
-      if (v0 == 0) {
-        double rmax = 0.0;
-        for (int k = 0; k < NL; ++k) rmax = fmax(rmax, fabs(L[ORD + k]));
-        for (int k = 0; k < NL; ++k)
-          if (!(fabs(L[ORD + k]) > 1e-12 * rmax)) fault |= 2;
-      }
       double po[NL];
 #pragma unroll
-      for (int l = 0; l < NL; ++l) po[l] = y[l] / L[OSC + l];
+      for (int l = 0; l < NL; ++l) po[l] = L[OP + sl * NL + l];
       // sectorial P1 polynomials
       double ps[NS][D];
 #pragma unroll
