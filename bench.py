@@ -12,10 +12,12 @@ more workloads are measured and reported under "extras": the small 2-D M=2
 mesh (8,192 triangles, 4 Euler variables) as launch latency p50/p99, the 3-D
 M=3 mesh (1,572,864 Kuhn tetrahedra, 5 variables) as throughput, and (unless
 --no-batch) a batch of 64 uneven meshes of mixed dimension and degree as one
-FP32 graph launch against per-mesh FP64 launches, and (unless
+FP32 graph launch against per-mesh FP64 launches, (unless
 --serve-seconds 0) the serving loop: 200 registered meshes, HBM budget half
 their footprint, Poisson request arrivals; latency p50/p99/p99.9 against a
-serial FP64 server.
+serial FP64 server, and (unless --no-moving) the moving-mesh path on the 2-D
+and 3-D workloads with moved vertices: operators rebuilt from the vertices
+in every call, FP64 arithmetic, against the stored-operator path.
 """
 from __future__ import annotations
 
@@ -33,9 +35,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CWENO cells·vars reconstructed/s + % HBM peak, FP64 vs FP32; p99 latency"
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_TFS = 78.6
 SEED = 16120935
 CSRC = os.path.join(ROOT, "paper_1612_09335_amd", "csrc")
 KERNEL_SRCS = ["reconstruct_kernel.hpp", "halo_kernel.hpp", "dispatch.hpp", "kernels.hip", "gen_sigma.cpp"]
+MOVING_SRCS = ["moving_kernel.hpp", "moving.hpp", "moving_kernels.hip"]
 
 
 def log(*a):
@@ -57,14 +61,69 @@ def algorithmic_bytes_per_cell(d, M, n_e, nv, s):
     return s * ((nb - 1) * (n_e - 1) + (d + 1) * d * d) + 4 * (n_e - 1) + d * (d + 1) + nv * s * (1 + nb)
 
 
-def kernel_source_hash():
+def gm_points(d, M):
+    """Points of the Grundmann-Moller rule exact to degree M on the d-simplex."""
+    from math import comb
+    s = M // 2
+    return sum(comb(s - i + d, d) for i in range(s + 1))
+
+
+def moving_flops_per_cell(d, M, n_e, nv):
+    """FP64 operations one moving-mesh reconstruction spends per cell.
+
+    Quadrature of the rows: (n_e-1) cells x nq points x (8 per basis function
+    evaluated + 2 per accumulated average); Householder QR of the
+    (n_e-1) x (nb-1) matrix, 2 m n^2 - 2/3 n^3; per variable the reflections
+    (4 per entry of the lower trapezoid) and the back substitution (n^2), and
+    the blend (the quadratic form, n^2, plus 10 per polynomial).
+    """
+    nb = n_basis(d, M)
+    m, n = n_e - 1, nb - 1
+    quad = m * gm_points(d, M) * (8 * nb + 2 * n)
+    qr = 2 * m * n * n - 2 * n ** 3 / 3
+    per_var = 4 * (m * n - n * (n - 1) / 2) + n * n + n * n + 10 * (d + 2)
+    return quad + qr + nv * per_var
+
+
+def measure_moving(torch, C, m, Q, M, label, d, steps, stored_ms):
+    """Moving-mesh path: operators rebuilt from moved vertices in every call."""
+    from synthetic import moved_vertices
+    dev = torch.device("cuda:0")
+    nv = Q.shape[0]
+    t0 = time.perf_counter()
+    lm = C.Mesh(m.vertices, m.cells, M, periodic=m.box, ops="none", moving=True)
+    t_reg = time.perf_counter() - t0
+    V = torch.tensor(moved_vertices(m, 0.2, 0.1), device=dev)
+    flops = moving_flops_per_cell(d, M, lm.n_e, nv) * m.n_cells
+    out = {"workload": f"{label} with every vertex moved (smooth periodic shear, gradient 0.2); stencils of the "
+                       f"connectivity, operators rebuilt per call", "registration_s": t_reg,
+           "device_bytes": lm.device_bytes, "flops_per_launch": flops}
+    fault = torch.zeros(1, dtype=torch.int32, device=dev)
+    for tag, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        q = torch.tensor(Q, dtype=tdt, device=dev)
+        o = torch.empty((nv, lm.n_basis, lm.n_cells), dtype=tdt, device=dev)
+        ms = time_loop(torch, lambda: lm.reconstruct_moving(V, q, out=o, fault=fault), steps, 2)
+        tf = flops / (ms * 1e-3) / 1e12
+        out[tag] = {"ms_per_step": ms, "value": m.n_cells * nv / (ms * 1e-3),
+                    "vs_stored_operators": ms / stored_ms[tag],
+                    "roofline": dict(bound="alu", achieved=tf, peak=FP64_VECTOR_TFS, unit="TFLOP/s",
+                                     frac=tf / FP64_VECTOR_TFS,
+                                     traffic=load_traffic("moving_" + tag, MOVING_SRCS) if d == 2 else None)}
+        log(f"moving {label} {tag}: {ms:.3f} ms ({out[tag]['value']:.3e} cells*vars/s, {tf:.2f} TFLOP/s FP64, "
+            f"{ms / stored_ms[tag]:.1f}x the stored-operator launch)")
+        del q, o
+    out["fault"] = int(fault.item())
+    return out
+
+
+def kernel_source_hash(names=KERNEL_SRCS):
     h = hashlib.sha256()
-    for name in KERNEL_SRCS:
+    for name in names:
         h.update(open(os.path.join(CSRC, name), "rb").read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(tag):
+def load_traffic(tag, names=KERNEL_SRCS):
     """HBM bytes per launch measured by rocprofv3 counters, if still current."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -73,7 +132,7 @@ def load_traffic(tag):
         rec = json.load(open(path)).get(tag)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("kernel_source_sha") != kernel_source_hash():
+    if not rec or rec.get("kernel_source_sha") != kernel_source_hash(names):
         return None
     return rec.get("bytes_per_launch")
 
@@ -303,8 +362,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--quick", action="store_true", help="only the main workload")
+    ap.add_argument("--quick", action="store_true", help="only the main workload (and its moving-mesh form)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-mesh batch workload")
+    ap.add_argument("--no-moving", action="store_true", help="skip the moving-mesh workloads")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the serving run (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -341,6 +401,13 @@ def main():
         res[tag]["roofline"]["traffic"] = load_traffic(tag)
 
     extras = {}
+    if not args.no_moving:
+        try:
+            stored2 = {tag: res[tag]["ms_per_step"] for tag in ("f64", "f32")}
+            extras["moving_tri512_M3_nv9"] = measure_moving(torch, C, m, Q, M, "tri512 M3", d, 10, stored2)
+        except Exception as exc:          # reported, never fatal to the headline line
+            log(f"moving workload failed: {exc!r}")
+            extras["moving_tri512_M3_nv9"] = {"error": repr(exc)}
     if not args.quick:
         # small mesh: launch-bound, reported as latency
         m1 = tri_mesh(64, 0.15, 16120934)
@@ -361,7 +428,15 @@ def main():
         for tag in ("f64", "f32"):
             extras["kuhn64_M3_nv5"][tag] = {k: r3[tag][k] for k in ("value", "ms_per_step", "latency_ms", "roofline",
                                                                    "variant", "flushed_ms", "flushed_frac")}
+        stored3 = {tag: r3[tag]["ms_per_step"] for tag in ("f64", "f32")}
         del r3
+        if not args.no_moving:
+            try:
+                extras["moving_kuhn64_M3_nv5"] = measure_moving(torch, C, m3, Q3, 3, "kuhn64 M3", 3, 5, stored3)
+            except Exception as exc:          # reported, never fatal to the headline line
+                log(f"moving workload failed: {exc!r}")
+                extras["moving_kuhn64_M3_nv5"] = {"error": repr(exc)}
+        del m3, Q3
         if not args.no_batch:
             try:
                 extras["batch64_mixed"] = measure_batch(torch, C, 20)
@@ -405,6 +480,7 @@ def main():
         "precompute_s": res["precompute_s"],
         "extras": extras,
         "kernel_source_sha": kernel_source_hash(),
+        "moving_kernel_source_sha": kernel_source_hash(MOVING_SRCS),
     }
     print(json.dumps(line))
 
