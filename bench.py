@@ -17,7 +17,9 @@ FP32 graph launch against per-mesh FP64 launches, (unless
 their footprint, Poisson request arrivals; latency p50/p99/p99.9 against a
 serial FP64 server, and (unless --no-moving) the moving-mesh path on the 2-D
 and 3-D workloads with moved vertices: operators rebuilt from the vertices
-in every call, FP64 arithmetic, against the stored-operator path.
+in every call, FP64 arithmetic, against the stored-operator path.  The point
+values of the benchmark reconstruction at the face Gauss points are timed
+with every run.
 """
 from __future__ import annotations
 
@@ -113,6 +115,37 @@ def measure_moving(torch, C, m, Q, M, label, d, steps, stored_ms):
             f"{ms / stored_ms[tag]:.1f}x the stored-operator launch)")
         del q, o
     out["fault"] = int(fault.item())
+    return out
+
+
+def face_gauss_points(d, n):
+    """n-point Gauss-Legendre points on every edge of the reference triangle (d = 2)."""
+    g, _ = np.polynomial.legendre.leggauss(n)
+    t = 0.5 * (g + 1.0)
+    verts = np.vstack([np.zeros(d), np.eye(d)])
+    return np.vstack([np.outer(1 - t, verts[a]) + np.outer(t, verts[b])
+                      for a in range(d + 1) for b in range(a + 1, d + 1)])
+
+
+def measure_evaluate(torch, C, lm, Q, M, d, steps):
+    """Point values of the benchmark reconstruction at the face Gauss points."""
+    P = face_gauss_points(d, M + 1)
+    pts = C.Points(d, M, P)
+    nv, nb = Q.shape[0], lm.n_basis
+    out = {"workload": f"coefficients of the benchmark reconstruction evaluated at {len(P)} face points "
+                       f"({M + 1} Gauss-Legendre points on each edge)", "n_points": len(P)}
+    for tag, tdt, s in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+        q = torch.tensor(Q, dtype=tdt, device="cuda:0")
+        co = lm.reconstruct(q)
+        vals = torch.empty((nv, len(P), lm.n_cells), dtype=tdt, device="cuda:0")
+        ms = time_loop(torch, lambda: lm.evaluate(pts, co, out=vals), steps, 3)
+        alg = lm.n_cells * nv * s * (nb + len(P))
+        gbs = alg / (ms * 1e-3) / 1e9
+        out[tag] = {"ms_per_step": ms, "value": lm.n_cells * nv / (ms * 1e-3),
+                    "roofline": dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                                     frac=gbs / HBM_PEAK_GBS, traffic=None, algorithmic_bytes_per_launch=alg)}
+        log(f"evaluate {tag}: {ms:.4f} ms, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
+        del q, co, vals
     return out
 
 
@@ -401,6 +434,11 @@ def main():
         res[tag]["roofline"]["traffic"] = load_traffic(tag)
 
     extras = {}
+    try:
+        extras["evaluate_tri512_M3_nv9"] = measure_evaluate(torch, C, res["mesh"], Q, M, d, 50)
+    except Exception as exc:          # reported, never fatal to the headline line
+        log(f"evaluate workload failed: {exc!r}")
+        extras["evaluate_tri512_M3_nv9"] = {"error": repr(exc)}
     if not args.no_moving:
         try:
             stored2 = {tag: res[tag]["ms_per_step"] for tag in ("f64", "f32")}

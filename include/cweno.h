@@ -242,6 +242,37 @@ cweno_status cweno_reconstruct_moving(const cweno_mesh* mesh, const double* vert
                                       void* omega, int* fault, void* hip_stream);
 
 /*
+ * Point values of the reconstruction (the predictor and the fluxes use the
+ * reconstruction polynomial at quadrature points of each cell and of its
+ * faces, Sec. 2.2-2.3).
+ *
+ * cweno_points_create   register a point set: n_points reference coordinates
+ *                       (host, [n_points][dim] doubles; e.g. face or volume
+ *                       quadrature points on the reference simplex), the same
+ *                       relative place in every cell since every cell's
+ *                       coefficients live in its own reference frame.  The
+ *                       basis values phi[q][l] = psi_l(xi_q) (the library's
+ *                       basis order) are computed once on the host in FP64
+ *                       and kept on the current device in FP64 and FP32.
+ *                       1 <= n_points <= 4096, degree 1..4.
+ * cweno_points_basis    host copy of phi, [n_points][n_basis] (for tests)
+ * cweno_points_destroy  release it (NULL accepted)
+ * cweno_evaluate        values[v][q][i] = sum_l phi[q][l] coeffs[v][l][i] for
+ *                       every cell i of the mesh: coeffs as written by
+ *                       cweno_reconstruct (device, [n_vars][n_basis][n_cells]),
+ *                       values device [n_vars][n_points][n_cells], both of
+ *                       dtype; asynchronous on hip_stream; the point set must
+ *                       have the mesh's dimension and degree; the buffers must
+ *                       not overlap.  Errors: CWENO_E_ARG, CWENO_E_HIP.
+ */
+typedef struct cweno_points cweno_points;
+cweno_status cweno_points_create(int dim, int degree, int n_points, const double* ref_points, cweno_points** out);
+cweno_status cweno_points_basis(const cweno_points* points, double* phi);
+cweno_status cweno_points_destroy(cweno_points* points);
+cweno_status cweno_evaluate(const cweno_mesh* mesh, const cweno_points* points, int n_vars, cweno_dtype dtype,
+                            const void* coeffs, void* values, void* hip_stream);
+
+/*
  * Kernel variants and their autotuner.
  *
  * The reconstruction kernel exists in several variants (cweno_num_variants()).

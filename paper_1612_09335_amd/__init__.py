@@ -26,7 +26,8 @@ STATUS = {0: "CWENO_OK", -1: "CWENO_E_ARG", -2: "CWENO_E_MESH", -3: "CWENO_E_STE
           -8: "CWENO_E_HIP", -9: "CWENO_E_BUSY", -10: "CWENO_E_CANCELLED"}
 
 SYMBOLS = ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_mesh_tables",
-           "cweno_mesh_operators", "cweno_reconstruct", "cweno_reconstruct_moving", "cweno_status_string",
+           "cweno_mesh_operators", "cweno_reconstruct", "cweno_reconstruct_moving", "cweno_points_create",
+           "cweno_points_basis", "cweno_points_destroy", "cweno_evaluate", "cweno_status_string",
            "cweno_last_error",
            "cweno_abi_version", "cweno_num_variants", "cweno_mesh_set_variant", "cweno_mesh_get_variant",
            "cweno_mesh_tune", "cweno_batch_create", "cweno_batch_run", "cweno_batch_info", "cweno_batch_group",
@@ -70,6 +71,10 @@ def _load():
     lib.cweno_mesh_operators.argtypes = [vp, i64, vp, vp, vp]
     lib.cweno_reconstruct.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
     lib.cweno_reconstruct_moving.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp]
+    lib.cweno_points_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(vp)]
+    lib.cweno_points_basis.argtypes = [vp, vp]
+    lib.cweno_points_destroy.argtypes = [vp]
+    lib.cweno_evaluate.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
     lib.cweno_mesh_set_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.cweno_mesh_get_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -253,6 +258,27 @@ class Mesh:
                                             None if fault is None else fault.data_ptr(), _stream_ptr(stream)))
         return out
 
+    def evaluate(self, points, coeffs, out=None, stream=None):
+        """cweno_evaluate: coeffs [n_vars, n_basis, n_cells] -> values [n_vars, n_points, n_cells]."""
+        import torch
+        if (not coeffs.is_cuda or coeffs.dim() != 3 or tuple(coeffs.shape[1:]) != (self.n_basis, self.n_cells)
+                or not coeffs.is_contiguous()):
+            raise ValueError("coeffs must be a contiguous CUDA tensor [n_vars, n_basis, n_cells]")
+        dt = {torch.float64: F64, torch.float32: F32}.get(coeffs.dtype)
+        if dt is None:
+            raise ValueError("coeffs must be float64 or float32")
+        nv = coeffs.shape[0]
+        shape = (nv, points.n_points, self.n_cells)
+        if out is None:
+            out = torch.empty(shape, dtype=coeffs.dtype, device=coeffs.device)
+        elif tuple(out.shape) != shape or out.dtype != coeffs.dtype or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous {coeffs.dtype} tensor {shape}")
+        if stream is None:
+            stream = torch.cuda.current_stream(coeffs.device)
+        _check(lib.cweno_evaluate(self._h, points._h, nv, dt, coeffs.data_ptr(), out.data_ptr(),
+                                  _stream_ptr(stream)))
+        return out
+
     # ---------------------------------------------------------------- variants
     def set_variant(self, dtype: str, vb: int, variant: int):
         _check(lib.cweno_mesh_set_variant(self._h, {"f64": F64, "f32": F32}[dtype], vb, variant))
@@ -276,6 +302,32 @@ class Mesh:
         _check(lib.cweno_mesh_tune(self._h, q.shape[0], dt, q.data_ptr(), out.data_ptr(), repeats,
                                    _stream_ptr(stream), ctypes.byref(ms)))
         return ms.value
+
+
+class Points:
+    """A registered set of reference points (cweno_points_create)."""
+
+    def __init__(self, dim: int, degree: int, ref_points):
+        P = np.ascontiguousarray(ref_points, dtype=np.float64)
+        if P.ndim != 2 or P.shape[1] != dim:
+            raise ValueError(f"ref_points must be [n_points, {dim}]")
+        self.dim, self.degree, self.n_points = int(dim), int(degree), int(P.shape[0])
+        self.ref_points = P
+        h = ctypes.c_void_p()
+        _check(lib.cweno_points_create(self.dim, self.degree, self.n_points, P.ctypes.data, ctypes.byref(h)))
+        self._h = h
+
+    def basis(self):
+        """phi [n_points, n_basis]: the basis functions at the points (FP64, host)."""
+        phi = np.empty((self.n_points, n_basis(self.degree, self.dim)))
+        _check(lib.cweno_points_basis(self._h, phi.ctypes.data))
+        return phi
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and lib is not None:
+            lib.cweno_points_destroy(h)
+            self._h = None
 
 
 def num_variants() -> int:
@@ -434,4 +486,4 @@ def _stream_ptr(stream):
     return getattr(stream, "cuda_stream", None)
 
 
-__all__ = ["Mesh", "CwenoError", "n_basis", "lib", "LIB_PATH", "SYMBOLS"]
+__all__ = ["Mesh", "Points", "CwenoError", "n_basis", "lib", "LIB_PATH", "SYMBOLS"]
