@@ -27,11 +27,16 @@ Parity status of each part (what pins it, from outside the oracle itself):
                   jumps.
 * dropped-sector rule -- parity unpinned (the paper assumes non-degenerate
                   stencils and gives no rule).
+* classical WENO (weno.py, the paper's comparison scheme) -- every stencil's
+                  polynomial reproduces degree-M data, so the blend does;
+                  conservation; cone and reverse-cone membership re-derived by
+                  independent barycentric solves; stencil sizes.
 """
 from .basis import n_basis, sigma_matrix, evaluate as evaluate_basis, index_list
 from .cweno import CwenoOracle, Options, linear_weights, stencil_size, evaluate_polynomial
 from .stencils import StencilError, face_neighbours
+from .weno import WenoOracle
 
 __all__ = ["n_basis", "sigma_matrix", "evaluate_basis", "index_list", "CwenoOracle",
            "Options", "linear_weights", "stencil_size", "evaluate_polynomial",
-           "StencilError", "face_neighbours"]
+           "StencilError", "face_neighbours", "WenoOracle"]

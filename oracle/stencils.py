@@ -115,6 +115,34 @@ def in_cone(geo: Geometry, i: int, s: int, j: int) -> bool:
     return all(b[m] > CONE_TOL for m in range(geo.d + 1) if m != s)
 
 
+def in_reverse_cone(geo: Geometry, i: int, s: int, j: int) -> bool:
+    """The cone opposite to cone s at vertex s (apex X_s, spanned by the edges
+    pointing away from the other vertices): b_m < -1e-12 for every m != s."""
+    X = geo.cell_vertices(i)
+    ci = geo.centroid(i)
+    o = geo.offset(i, j)
+    p = tuple(ci[a] + o[a] for a in range(geo.d))
+    b = barycentric(X, p)
+    return all(b[m] < -CONE_TOL for m in range(geo.d + 1) if m != s)
+
+
+def weno_stencils(geo: Geometry, nbr: np.ndarray, i: int, n_e: int):
+    """The d+1 forward and d+1 reverse sector stencils of the classical
+    unstructured WENO reconstruction, n_e cells each (i first), filled by the
+    same ring procedure restricted to cone s or to its reverse; None when a
+    stencil cannot be filled."""
+    d = geo.d
+    out = []
+    for pred in (in_cone, in_reverse_cone):
+        for s in range(d + 1):
+            sel = ring_fill(geo, nbr, i, n_e, admit=lambda j, s=s, pred=pred: pred(geo, i, s, j))
+            if sel is not None:
+                for j in sel[1:]:
+                    _check_reach(geo, i, j)
+            out.append(sel)
+    return out
+
+
 def sector_stencils(geo: Geometry, nbr: np.ndarray, i: int, rule: str = "cone"):
     """List of d+1 sectors; each is a list of d+1 cells (i first) or None (unfillable)."""
     d = geo.d
