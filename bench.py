@@ -19,7 +19,9 @@ serial FP64 server, and (unless --no-moving) the moving-mesh path on the 2-D
 and 3-D workloads with moved vertices: operators rebuilt from the vertices
 in every call, FP64 arithmetic, against the stored-operator path.  The point
 values of the benchmark reconstruction at the face Gauss points are timed
-with every run.
+with every run, and (unless --no-weno) the classical unstructured WENO scheme
+the paper compares CWENO with runs on the benchmark workload (memory and time
+against CWENO).
 """
 from __future__ import annotations
 
@@ -147,6 +149,44 @@ def measure_evaluate(torch, C, lm, Q, M, d, steps):
         log(f"evaluate {tag}: {ms:.4f} ms, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
         del q, co, vals
     return out
+
+
+def measure_weno(torch, C, m, Q, M, d, steps, cweno_ms, cweno_n_e):
+    """The classical unstructured WENO scheme on the benchmark workload (FP64)."""
+    nv = Q.shape[0]
+    t0 = time.perf_counter()
+    lm = C.Mesh(m.vertices, m.cells, M, periodic=m.box, weno=True)
+    t_pre = time.perf_counter() - t0
+    nb, n_e, n_s = lm.n_basis, lm.n_e, 1 + 2 * (d + 1)
+    nl, ne1 = nb - 1, n_e - 1
+    vbmax = 4 if nl <= 9 else (2 if nl <= 19 else 1)
+    passes = -(-nv // vbmax)
+    weno_entries = n_s * nl * ne1
+    cweno_entries = nl * (cweno_n_e - 1) + (d + 1) * d * d
+    alg = (8 * weno_entries + 4 * n_s * ne1 + 2 + nv * 8 * (1 + nb)) * m.n_cells
+    streamed = (passes * (8 * weno_entries + 4 * n_s * ne1 + 2) + nv * 8 * (1 + nb)) * m.n_cells
+    q = torch.tensor(Q, device="cuda:0")
+    out = torch.empty((nv, nb, lm.n_cells), dtype=torch.float64, device="cuda:0")
+    ms = time_loop(torch, lambda: lm.reconstruct(q, out=out), steps, 3)
+    gbs = alg / (ms * 1e-3) / 1e9
+    M_ = nb
+    paper_ratio = ((1 + 2 * (d + 1)) * d * M_ * M_) / (d * M_ * M_ + (d + 1) * (d + 1) ** 2)
+    r = {"workload": f"classical unstructured WENO on the benchmark mesh: {n_s} stencils of n_e={n_e} cells "
+                     f"(central, {d + 1} forward and {d + 1} reverse cone sectors), degree {M} each, FP64",
+         "precompute_s": t_pre, "device_bytes": lm.device_bytes, "n_dropped": lm.n_dropped,
+         "operator_entries_per_cell": weno_entries, "cweno_operator_entries_per_cell": cweno_entries,
+         "memory_ratio_weno_over_cweno": weno_entries / cweno_entries,
+         "paper_formula_ratio": paper_ratio,
+         "ms_per_step": ms, "value": m.n_cells * nv / (ms * 1e-3),
+         "time_ratio_weno_over_cweno_f64": ms / cweno_ms, "operator_passes": passes,
+         "roofline": dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS,
+                          traffic=None, algorithmic_bytes_per_launch=alg, streamed_bytes_per_launch=streamed,
+                          streamed_frac=streamed / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)}
+    log(f"weno: precompute {t_pre:.1f} s, {lm.device_bytes / 1e9:.2f} GB on the device, {ms:.3f} ms "
+        f"({ms / cweno_ms:.1f}x CWENO FP64), operators {weno_entries / cweno_entries:.2f}x CWENO's "
+        f"(paper formula {paper_ratio:.2f}x), streamed {100 * r['roofline']['streamed_frac']:.1f}% of HBM peak")
+    del lm, q, out
+    return r
 
 
 def kernel_source_hash(names=KERNEL_SRCS):
@@ -398,6 +438,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="only the main workload (and its moving-mesh form)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-mesh batch workload")
     ap.add_argument("--no-moving", action="store_true", help="skip the moving-mesh workloads")
+    ap.add_argument("--no-weno", action="store_true", help="skip the classical WENO comparison")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the serving run (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -447,6 +488,13 @@ def main():
             log(f"moving workload failed: {exc!r}")
             extras["moving_tri512_M3_nv9"] = {"error": repr(exc)}
     if not args.quick:
+        if not args.no_weno:
+            try:
+                extras["weno_tri512_M3_nv9"] = measure_weno(torch, C, m, Q, M, d, 10, res["f64"]["ms_per_step"],
+                                                            res["n_e"])
+            except Exception as exc:          # reported, never fatal to the headline line
+                log(f"weno workload failed: {exc!r}")
+                extras["weno_tri512_M3_nv9"] = {"error": repr(exc)}
         # small mesh: launch-bound, reported as latency
         m1 = tri_mesh(64, 0.15, 16120934)
         Q1 = workload_fields(m1, "euler2d_sod", 16120934)

@@ -81,6 +81,8 @@ typedef enum {
 #define CWENO_FLAG_LINEAR_WEIGHTS 4u  /* diagnostic: omega := lambda (w = P_opt)                   */
 #define CWENO_FLAG_MOVING 8u          /* keep connectivity and stencils on the device for
                                          cweno_reconstruct_moving                                */
+#define CWENO_FLAG_WENO 16u           /* the classical unstructured WENO scheme instead of CWENO
+                                         (see cweno_mesh_weno_tables)                            */
 
 /* Reconstruction options.  A zero-initialised struct gives the defaults. */
 typedef struct {
@@ -271,6 +273,28 @@ cweno_status cweno_points_basis(const cweno_points* points, double* phi);
 cweno_status cweno_points_destroy(cweno_points* points);
 cweno_status cweno_evaluate(const cweno_mesh* mesh, const cweno_points* points, int n_vars, cweno_dtype dtype,
                             const void* coeffs, void* values, void* hip_stream);
+
+/*
+ * Classical unstructured WENO (CWENO_FLAG_WENO at cweno_mesh_create): the
+ * scheme the paper compares CWENO with in its efficiency discussion (Sec. 4),
+ * built on the same geometry, quadrature and least squares.  n_s = 1 + 2(d+1)
+ * stencils of n_e cells each: the central stencil, d+1 forward sectors (the
+ * CWENO cones, filled to n_e cells) and d+1 reverse sectors (the opposite cone
+ * at each vertex: every barycentric coordinate but the s-th below -1e-12);
+ * each gives a degree-M polynomial by the constrained least squares of eq.
+ * CWENO:Popt on its own stencil; indicators with the same Sigma; linear
+ * weights lambda0 (central) and (1 - lambda0)/(2(d+1)) per sector (lambda0 < 0:
+ * 1e5 against 1 per sector, normalised); omega~ = lambda/(sigma+eps)^r,
+ * w = sum omega~ P / sum omega~.  An unfillable stencil is dropped.  Such a
+ * mesh keeps FP64 operators only (ops must be CWENO_OPS_F64; no moving form,
+ * no CWENO-only flags); cweno_reconstruct runs the WENO kernel (FP64, sigma and
+ * omega must be NULL); it cannot join a batch or a server.
+ *
+ * cweno_mesh_weno_tables  *n_stencils = n_s; stencils (may be NULL) receives
+ *                         the host table [n_cells][n_s][n_e] int32 (the cell
+ *                         first; a row of -1 for an unfillable stencil)
+ */
+cweno_status cweno_mesh_weno_tables(const cweno_mesh* mesh, int* n_stencils, int32_t* stencils);
 
 /*
  * Kernel variants and their autotuner.

@@ -14,9 +14,10 @@ only this outline; the readings taken here:
 * each polynomial: the constrained least squares of eq. CWENO:Popt on its
   own stencil (its cell average matched exactly);
 * indicators sigma_j = p_j^T Sigma p_j with the universal Sigma of Sec. 2.1;
-* linear weights: lambda_0 for the central stencil (default 0.95), the rest
-  (1 - lambda_0) / (2(d+1)) each; a stencil that cannot be filled is dropped
-  and the others renormalised;
+* linear weights: lambda_0 for the central stencil (default 0.95; 'paper':
+  1e5 against 1 per sector stencil, normalised), the rest (1 - lambda_0) /
+  (2(d+1)) each; a stencil that cannot be filled is dropped and the others
+  renormalised;
 * omega~_j = lambda_j / (sigma_j + eps)^r, omega = omega~ / sum omega~,
   w = sum_j omega_j P_j (eqs. weights, weights2 with all polynomials of
   degree M).
@@ -36,7 +37,10 @@ class WenoOracle:
         self.cw = CwenoOracle(vertices, cells, box, opts, nbr=nbr)
         self.d, self.M, self.nb, self.n_e = self.cw.d, self.cw.M, self.cw.nb, self.cw.n_e
         self.n_s = 1 + 2 * (self.d + 1)
-        l0 = 0.95 if opts.lambda0 == 0.0 else float(opts.lambda0)
+        if opts.lambda0 == "paper":       # 1e5 for the central stencil, 1 per sector stencil, normalised
+            l0 = 1e5 / (1e5 + self.n_s - 1)
+        else:
+            l0 = 0.95 if opts.lambda0 == 0.0 else float(opts.lambda0)
         self.lam = np.array([l0] + [(1.0 - l0) / (self.n_s - 1)] * (self.n_s - 1))
         self.opts = opts
         self._cache = {}

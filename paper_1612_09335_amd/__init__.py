@@ -19,14 +19,14 @@ LIB_PATH = os.path.join(_PKG, "libcweno.so")
 F64, F32 = 0, 1
 OPS = {"f64": 0, "f32": 1, "both": 2, "none": 3}
 SECTOR_RULES = {"cone": 0, "face": 1}
-FLAG_HOST_ONLY, FLAG_SIGMA0_POPT, FLAG_LINEAR_WEIGHTS, FLAG_MOVING = 1, 2, 4, 8
+FLAG_HOST_ONLY, FLAG_SIGMA0_POPT, FLAG_LINEAR_WEIGHTS, FLAG_MOVING, FLAG_WENO = 1, 2, 4, 8, 16
 
 STATUS = {0: "CWENO_OK", -1: "CWENO_E_ARG", -2: "CWENO_E_MESH", -3: "CWENO_E_STENCIL",
           -4: "CWENO_E_RANK", -5: "CWENO_E_PERIODIC", -6: "CWENO_E_NOMEM", -7: "CWENO_E_BUDGET",
           -8: "CWENO_E_HIP", -9: "CWENO_E_BUSY", -10: "CWENO_E_CANCELLED"}
 
 SYMBOLS = ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_mesh_tables",
-           "cweno_mesh_operators", "cweno_reconstruct", "cweno_reconstruct_moving", "cweno_points_create",
+           "cweno_mesh_operators", "cweno_mesh_weno_tables", "cweno_reconstruct", "cweno_reconstruct_moving", "cweno_points_create",
            "cweno_points_basis", "cweno_points_destroy", "cweno_evaluate", "cweno_status_string",
            "cweno_last_error",
            "cweno_abi_version", "cweno_num_variants", "cweno_mesh_set_variant", "cweno_mesh_get_variant",
@@ -71,6 +71,7 @@ def _load():
     lib.cweno_mesh_operators.argtypes = [vp, i64, vp, vp, vp]
     lib.cweno_reconstruct.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
     lib.cweno_reconstruct_moving.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp]
+    lib.cweno_mesh_weno_tables.argtypes = [vp, ctypes.POINTER(ctypes.c_int), vp]
     lib.cweno_points_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(vp)]
     lib.cweno_points_basis.argtypes = [vp, vp]
     lib.cweno_points_destroy.argtypes = [vp]
@@ -108,7 +109,7 @@ def _load():
     lib.cweno_server_pause.argtypes = [vp, ctypes.c_int]
     lib.cweno_server_destroy.argtypes = [vp]
     for name in ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_mesh_tables",
-                 "cweno_mesh_operators", "cweno_reconstruct", "cweno_mesh_set_variant",
+                 "cweno_mesh_operators", "cweno_mesh_weno_tables", "cweno_reconstruct", "cweno_mesh_set_variant",
                  "cweno_mesh_get_variant", "cweno_mesh_tune", "cweno_num_variants", "cweno_batch_create",
                  "cweno_batch_run", "cweno_batch_info", "cweno_batch_group", "cweno_batch_destroy",
                  "cweno_server_create", "cweno_server_register", "cweno_server_register_mesh",
@@ -138,7 +139,7 @@ class Mesh:
     def __init__(self, vertices, cells, degree: int, periodic=(0.0, 0.0, 0.0), stencil_factor: float = 0.0,
                  lambda0: float = 0.0, eps: float = 0.0, r: int = 0, ops: str = "f64",
                  sector_rule: str = "cone", sigma0_popt: bool = False, linear_weights: bool = False,
-                 host_only: bool = False, moving: bool = False, stream=None):
+                 host_only: bool = False, moving: bool = False, weno: bool = False, stream=None):
         V = np.ascontiguousarray(vertices, dtype=np.float64)
         C = np.ascontiguousarray(cells, dtype=np.int32)
         self.dim = int(V.shape[1])
@@ -153,7 +154,9 @@ class Mesh:
         o.ops = OPS[ops]
         o.sector_rule = SECTOR_RULES[sector_rule]
         o.flags = ((FLAG_HOST_ONLY if host_only else 0) | (FLAG_SIGMA0_POPT if sigma0_popt else 0)
-                   | (FLAG_LINEAR_WEIGHTS if linear_weights else 0) | (FLAG_MOVING if moving else 0))
+                   | (FLAG_LINEAR_WEIGHTS if linear_weights else 0) | (FLAG_MOVING if moving else 0)
+                   | (FLAG_WENO if weno else 0))
+        self.weno = weno
         self.n_vertices = int(V.shape[0])
         self.moving = moving
         self.ops = ops
@@ -184,6 +187,14 @@ class Mesh:
         se = np.empty((self.n_cells, d + 1, d + 1), dtype=np.int32)
         _check(lib.cweno_mesh_tables(self._h, fn.ctypes.data, st.ctypes.data, se.ctypes.data))
         return dict(face_nbr=fn, stencil=st, sectors=se)
+
+    def weno_tables(self):
+        """Classical-WENO stencils [n_cells, n_s, n_e] (rows of -1: unfillable)."""
+        ns = ctypes.c_int()
+        _check(lib.cweno_mesh_weno_tables(self._h, ctypes.byref(ns), None))
+        st = np.empty((self.n_cells, ns.value, self.n_e), dtype=np.int32)
+        _check(lib.cweno_mesh_weno_tables(self._h, None, st.ctypes.data))
+        return st
 
     def operators(self, cell: int):
         """FP64 operators of one cell: pinv [nb-1, n_e-1], binv [d+1, d, d], sigma [nb-1, nb-1]."""

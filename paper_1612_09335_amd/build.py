@@ -23,7 +23,7 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["host_geometry.cpp", "host_basis.cpp", "host_operators.cpp", "host_halo.cpp"]
-HIP_SOURCES = ["abi.hip", "batch.hip", "server.hip", "moving.hip", "evaluate.hip"]
+HIP_SOURCES = ["abi.hip", "batch.hip", "server.hip", "moving.hip", "evaluate.hip", "weno.hip"]
 # kernels.hip and moving_kernels.hip are compiled once per (precision, dimension, degree)
 KERNEL_UNITS = [(tn, d, m) for tn in ("f64", "f32") for d in (2, 3) for m in (1, 2, 3, 4)]
 KERNEL_FILES = ["kernels", "moving_kernels"]

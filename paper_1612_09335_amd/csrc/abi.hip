@@ -2,6 +2,7 @@
 // precompute + device residency) and the reconstruction launch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -14,6 +15,7 @@
 #include "dispatch.hpp"
 #include "host.hpp"
 #include "mesh.hpp"
+#include "weno.hpp"
 
 namespace cweno_abi {
 
@@ -99,6 +101,42 @@ cweno_status check_reconstruct_args(const cweno_mesh* m, int n_vars, cweno_dtype
   return CWENO_OK;
 }
 
+// The classical WENO scheme on a WENO mesh (FP64; no indicator or weight output).
+cweno_status reconstruct_weno(const cweno_mesh* m, int n_vars, cweno_dtype dtype, const void* q, void* coeffs,
+                              void* sigma, void* omega, void* hip_stream) {
+  if (n_vars < 1) return fail(CWENO_E_ARG, "n_vars must be >= 1");
+  if (!q || !coeffs) return fail(CWENO_E_ARG, "q and coeffs must be device pointers");
+  if (!m->wpinv.p) return fail(CWENO_E_ARG, "mesh was built host-only");
+  if (dtype != CWENO_F64) return fail(CWENO_E_ARG, "the WENO scheme runs in FP64 only");
+  if (sigma || omega) return fail(CWENO_E_ARG, "the WENO scheme reports no indicators or weights");
+  const uint64_t cells = (uint64_t)m->nc * (uint64_t)n_vars;
+  if (overlap(q, cells * 8u, coeffs, cells * (uint64_t)m->nb * 8u))
+    return fail(CWENO_E_ARG, "q and coeffs must not overlap");
+  cweno::WParams p{};
+  p.q = (const double*)q;
+  p.out = (double*)coeffs;
+  p.pinv = (const double*)m->wpinv.p;
+  p.gidx = (const int32_t*)m->wgidx.p;
+  p.alive = (const uint16_t*)m->walive.p;
+  p.lam0 = m->lam[0];
+  p.lams = (1.0 - m->lam[0]) / (m->n_s - 1);
+  p.eps = m->eps;
+  p.nc = m->nc;
+  p.Np = m->Np;
+  p.NE1 = m->n_e - 1;
+  p.n_s = m->n_s;
+  p.r = m->r;
+  const int vbmax = cweno::weno_vb_max(m->d, m->M);
+  for (int v0 = 0; v0 < n_vars;) {
+    const int vb = std::min(vbmax, n_vars - v0);
+    p.v0 = v0;
+    const hipError_t e = cweno::launch_weno(m->d, m->M, p, vb, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    v0 += vb;
+  }
+  return CWENO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -150,6 +188,11 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
   if (o.ops < CWENO_OPS_F64 || o.ops > CWENO_OPS_NONE) return fail(CWENO_E_ARG, "bad ops");
   if ((o.flags & CWENO_FLAG_MOVING) && (o.flags & CWENO_FLAG_HOST_ONLY))
     return fail(CWENO_E_ARG, "a moving mesh lives on the device; it cannot be host-only");
+  const bool weno = (o.flags & CWENO_FLAG_WENO) != 0;
+  if (weno && (o.flags & CWENO_FLAG_MOVING)) return fail(CWENO_E_ARG, "the WENO scheme has no moving-mesh form");
+  if (weno && o.ops != CWENO_OPS_F64) return fail(CWENO_E_ARG, "the WENO scheme keeps FP64 operators only");
+  if (weno && (o.flags & (CWENO_FLAG_SIGMA0_POPT | CWENO_FLAG_LINEAR_WEIGHTS)))
+    return fail(CWENO_E_ARG, "CWENO-only flag given for a WENO mesh");
   if (o.sector_rule != CWENO_SECTOR_CONE && o.sector_rule != CWENO_SECTOR_FACE)
     return fail(CWENO_E_ARG, "bad sector rule");
   const double f = o.stencil_factor == 0.0 ? (double)dim : o.stencil_factor;
@@ -160,6 +203,7 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
     double tot = 1e5 + (dim + 1);
     m->lam[0] = 1e5 / tot;
     for (int s = 1; s <= dim + 1; ++s) m->lam[s] = 1.0 / tot;
+    if (o.flags & CWENO_FLAG_WENO) m->lam[0] = 1e5 / (1e5 + 2 * (dim + 1));   // 1e5 against 1 per sector stencil
   } else {
     double l0 = o.lambda0 == 0.0 ? 0.95 : o.lambda0;
     if (!(l0 > 0.0 && l0 < 1.0)) return fail(CWENO_E_ARG, "lambda0 must lie in (0, 1)");
@@ -186,7 +230,25 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
     cweno::face_adjacency(in, m->nbr);
     cweno::Stencils st;
     cweno::build_stencils(g, m->nbr, m->n_e, o.sector_rule, st);
-    if (o.ops != CWENO_OPS_NONE) cweno::build_operators(g, st, degree, m->op);
+    if (weno) {
+      cweno::WenoStencils ws;
+      cweno::build_weno_stencils(g, m->nbr, st, ws);
+      cweno::WenoOperators wop;
+      cweno::build_weno_operators(g, ws, degree, wop);
+      m->n_s = ws.n_s;
+      m->weno_cells.swap(ws.cells);
+      m->n_dropped = wop.n_dropped;
+      if (!(o.flags & CWENO_FLAG_HOST_ONLY)) {
+        hipStream_t s = (hipStream_t)hip_stream;
+        if (hipGetDevice(&m->device) != hipSuccess) return fail(CWENO_E_HIP, "no HIP device");
+        cweno_status ust;
+        if ((ust = upload(m->wpinv, wop.pinv.data(), wop.pinv.size() * 8, s, m->device_bytes))) return ust;
+        if ((ust = upload(m->wgidx, wop.gidx.data(), wop.gidx.size() * 4, s, m->device_bytes))) return ust;
+        if ((ust = upload(m->walive, wop.alive.data(), wop.alive.size() * 2, s, m->device_bytes))) return ust;
+      }
+    } else if (o.ops != CWENO_OPS_NONE) {
+      cweno::build_operators(g, st, degree, m->op);
+    }
     m->central.swap(st.central);
     m->sectors.swap(st.sectors);
   } catch (const cweno::Error& e) {
@@ -196,7 +258,7 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
   } catch (const std::exception& e) {
     return fail(CWENO_E_ARG, e.what());
   }
-  if (o.ops == CWENO_OPS_NONE) {   // no stored operators: only the moving-mesh path can run
+  if (o.ops == CWENO_OPS_NONE || weno) {   // no stored CWENO operators
     m->op.d = dim;
     m->op.M = degree;
     m->op.nb = m->nb;
@@ -216,9 +278,9 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
         (uint64_t)(m->G + 1) * Np * 4u >= lim)
       return fail(CWENO_E_ARG, "mesh too large for 32-bit offsets within an operator block (split it)");
   }
-  m->n_dropped = m->op.n_dropped;
+  if (!weno) m->n_dropped = m->op.n_dropped;
 
-  if (!(o.flags & CWENO_FLAG_HOST_ONLY)) {
+  if (!(o.flags & CWENO_FLAG_HOST_ONLY) && !weno) {
     hipStream_t s = (hipStream_t)hip_stream;
     if (hipGetDevice(&m->device) != hipSuccess) return fail(CWENO_E_HIP, "no HIP device");
     if (cweno_status cst = cweno_abi::configure_device_kernels()) return cst;
@@ -300,6 +362,14 @@ cweno_status cweno_mesh_tables(const cweno_mesh* m, int32_t* face_nbr, int32_t* 
   return CWENO_OK;
 }
 
+cweno_status cweno_mesh_weno_tables(const cweno_mesh* m, int* n_stencils, int32_t* stencils) {
+  if (!m) return fail(CWENO_E_ARG, "mesh is NULL");
+  if (m->n_s == 0) return fail(CWENO_E_ARG, "not a WENO mesh");
+  if (n_stencils) *n_stencils = m->n_s;
+  if (stencils) std::memcpy(stencils, m->weno_cells.data(), m->weno_cells.size() * 4);
+  return CWENO_OK;
+}
+
 cweno_status cweno_mesh_operators(const cweno_mesh* m, int64_t cell, double* pinv, double* binv, double* sigma) {
   if (!m) return fail(CWENO_E_ARG, "mesh is NULL");
   if (cell < 0 || cell >= m->nc) return fail(CWENO_E_ARG, "cell out of range");
@@ -319,6 +389,7 @@ cweno_status cweno_mesh_operators(const cweno_mesh* m, int64_t cell, double* pin
 
 cweno_status cweno_reconstruct(const cweno_mesh* m, int n_vars, cweno_dtype dtype, const void* q, void* coeffs,
                                void* sigma, void* omega, void* hip_stream) {
+  if (m && m->n_s > 0) return reconstruct_weno(m, n_vars, dtype, q, coeffs, sigma, omega, hip_stream);
   cweno_status st = check_reconstruct_args(m, n_vars, dtype, q, coeffs, sigma, omega);
   if (st) return st;
   hipStream_t s = (hipStream_t)hip_stream;

@@ -110,6 +110,30 @@ void sigma_matrix(int d, int M, std::vector<double>& S);   // [nb][nb]
 // Grundmann-Moller rule exact to `degree`: barycentric points [q][d+1], weights sum 1.
 void grundmann_moller(int d, int degree, std::vector<double>& lam, std::vector<double>& w);
 
+// Classical unstructured WENO (the scheme the paper compares CWENO with):
+// 1 + 2(d+1) stencils of n_e cells each -- the central stencil, the forward
+// cone sectors and the reverse cone sectors -- each with its own degree-M
+// least-squares polynomial.
+struct WenoStencils {
+  int n_s = 0, n_e = 0;
+  std::vector<int32_t> cells;    // [nc][n_s][n_e], the cell first; a row of -1 = unfillable
+};
+void build_weno_stencils(const Geometry& g, const std::vector<int32_t>& nbr, const Stencils& st,
+                         WenoStencils& ws);
+
+// Device layout of the WENO operators (structure of arrays, row stride Np):
+//   pinv[((j * (n_e-1) + k) * (nb-1) + l) * Np + i]   stencil j, cell k+1, coefficient l+1
+//   gidx[(j * (n_e-1) + k) * Np + i]                   stencil cell k+1 (the cell itself if j is dropped)
+//   alive[i]                                          bit j: stencil j kept
+struct WenoOperators {
+  int n_s = 0;
+  int64_t Np = 0, n_dropped = 0;
+  std::vector<double> pinv;
+  std::vector<int32_t> gidx;
+  std::vector<uint16_t> alive;
+};
+void build_weno_operators(const Geometry& g, const WenoStencils& ws, int M, WenoOperators& op);
+
 // Integer part of the operators: gather lists (the central stencil without
 // the cell, then sector cells outside it, padded with the cell), their length
 // G, the sector positions in them, and the universal Sigma.

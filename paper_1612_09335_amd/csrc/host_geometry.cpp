@@ -212,7 +212,10 @@ struct StencilCtx {
         throw Error(CWENO_E_PERIODIC, "stencil of cell " + std::to_string(i) +
                                           " reaches too far across the periodic box");
   }
-  bool in_cone(int64_t i, int s, int64_t j) const {
+  // Cone s of cell i (apex at vertex s, spanned by the edges to the other
+  // vertices): b_m > tol for every m != s; with reverse, the opposite cone at
+  // vertex s: b_m < -tol for every m != s.
+  bool in_cone(int64_t i, int s, int64_t j, bool reverse = false) const {
     const int d = g.d;
     P3 W[4];
     const double* X = &g.X[(size_t)i * (d + 1) * d];
@@ -231,13 +234,14 @@ struct StencilCtx {
       W[m] = p;
       double b = det_columns(d, W) / D;
       W[m] = keep;
-      if (!(b > kConeTol)) return false;
+      if (reverse ? !(b < -kConeTol) : !(b > kConeTol)) return false;
     }
     return true;
   }
 
-  // Breadth-first ring fill (cone sector s, or s < 0 for the central stencil).
-  bool fill(int64_t i, int n_target, int s, std::vector<int32_t>& sel) {
+  // Breadth-first ring fill (cone sector s, or s < 0 for the central stencil;
+  // reverse: the opposite cone of vertex s).
+  bool fill(int64_t i, int n_target, int s, std::vector<int32_t>& sel, bool reverse = false) {
     const int nvx = g.d + 1;
     sel.clear();
     sel.push_back((int32_t)i);
@@ -262,7 +266,7 @@ struct StencilCtx {
       frontier.clear();
       for (auto& pr : ring) {
         frontier.push_back(pr.second);
-        if (s < 0 || in_cone(i, s, pr.second)) {
+        if (s < 0 || in_cone(i, s, pr.second, reverse)) {
           sel.push_back(pr.second);
           if ((int)sel.size() == n_target) return true;
         }
@@ -306,6 +310,28 @@ void build_stencils(const Geometry& g, const std::vector<int32_t>& nbr, int n_e,
         for (size_t t = 1; t < sel.size(); ++t) ctx.check_reach(i, sel[t]);
         std::copy(sel.begin(), sel.end(), &st.sectors[((size_t)i * ns + s) * ns]);
       }
+    }
+  });
+}
+
+void build_weno_stencils(const Geometry& g, const std::vector<int32_t>& nbr, const Stencils& st,
+                         WenoStencils& ws) {
+  const int d = g.d, ns = d + 1, n_e = st.n_e, n_s = 1 + 2 * ns;
+  ws.n_s = n_s;
+  ws.n_e = n_e;
+  ws.cells.assign((size_t)g.nc * n_s * n_e, -1);
+  parallel_for(g.nc, [&](int64_t b, int64_t e) {
+    StencilCtx ctx(g, nbr);
+    std::vector<int32_t> sel;
+    for (int64_t i = b; i < e; ++i) {
+      int32_t* out = &ws.cells[(size_t)i * n_s * n_e];
+      std::copy(&st.central[(size_t)i * n_e], &st.central[(size_t)i * n_e] + n_e, out);
+      for (int rev = 0; rev < 2; ++rev)
+        for (int s = 0; s < ns; ++s) {
+          if (!ctx.fill(i, n_e, s, sel, rev == 1)) continue;
+          for (size_t t = 1; t < sel.size(); ++t) ctx.check_reach(i, sel[t]);
+          std::copy(sel.begin(), sel.end(), out + (size_t)(1 + rev * ns + s) * n_e);
+        }
     }
   });
 }

@@ -176,6 +176,43 @@ bool pseudo_inverse(int m, int n, const double* A, double* P) {
   return true;
 }
 
+// Row k of A' (k < nl): the averages of psi_1 .. psi_{nb-1} over cell list[k]
+// in cell i's reference frame (Jinv: inverse of its map), by the quadrature
+// (qlam, qw); A is row-major [nl][nb-1], psi a scratch of nb values.
+void stencil_rows(const Geometry& g, int64_t i, const double* Jinv, const int32_t* list, int nl, int M,
+                  const std::vector<double>& qlam, const std::vector<double>& qw, double* psi, double* A) {
+  const int d = g.d, ns = d + 1, nb = n_basis(M, d), nq = (int)qw.size();
+  const double* Xi = &g.X[(size_t)i * ns * d];
+  for (int k = 0; k < nl; ++k) {
+    int64_t j = list[k];
+    const double* Xj = &g.X[(size_t)j * ns * d];
+    double shift[3];
+    for (int a = 0; a < d; ++a) {
+      double dc = g.cen[(size_t)j * d + a] - g.cen[(size_t)i * d + a];
+      shift[a] = min_image(dc, g.box[a]) - dc;
+    }
+    double Y[4][3];
+    for (int v = 0; v < ns; ++v) {
+      double y[3];
+      for (int a = 0; a < d; ++a) y[a] = Xj[v * d + a] + shift[a] - Xi[a];
+      for (int r = 0; r < d; ++r) {
+        double s = 0.0;
+        for (int a = 0; a < d; ++a) s += Jinv[r * d + a] * y[a];
+        Y[v][r] = s;
+      }
+    }
+    double* row = &A[(size_t)k * (nb - 1)];
+    std::fill(row, row + nb - 1, 0.0);
+    for (int q = 0; q < nq; ++q) {
+      double xi[3] = {0, 0, 0};
+      for (int v = 0; v < ns; ++v)
+        for (int r = 0; r < d; ++r) xi[r] += qlam[(size_t)q * ns + v] * Y[v][r];
+      basis_eval(d, M, xi, psi);
+      for (int l = 1; l < nb; ++l) row[l - 1] += qw[q] * psi[l];
+    }
+  }
+}
+
 }  // namespace
 
 void build_gather(const Geometry& g, const Stencils& st, int M, Operators& op) {
@@ -245,7 +282,6 @@ void build_operators(const Geometry& g, const Stencils& st, int M, Operators& op
   op.binv.assign((size_t)ns * d * d * Np, 0.0);
   std::vector<double> qlam, qw;
   grundmann_moller(d, M, qlam, qw);
-  const int nq = (int)qw.size();
   std::vector<int64_t> dropped_per_cell(g.nc, 0);
 
   parallel_for(g.nc, [&](int64_t b, int64_t e) {
@@ -261,34 +297,7 @@ void build_operators(const Geometry& g, const Stencils& st, int M, Operators& op
       int nl = G;
       while (nl > NE1 && list[nl - 1] == (int32_t)i) --nl;   // padding entries are the cell itself
       // averages of psi_1.. over every gathered cell, in cell i's frame
-      for (int k = 0; k < nl; ++k) {
-        int64_t j = list[k];
-        const double* Xj = &g.X[(size_t)j * ns * d];
-        double shift[3];
-        for (int a = 0; a < d; ++a) {
-          double dc = g.cen[(size_t)j * d + a] - g.cen[(size_t)i * d + a];
-          shift[a] = min_image(dc, g.box[a]) - dc;
-        }
-        double Y[4][3];
-        for (int v = 0; v < ns; ++v) {
-          double y[3];
-          for (int a = 0; a < d; ++a) y[a] = Xj[v * d + a] + shift[a] - Xi[a];
-          for (int r = 0; r < d; ++r) {
-            double s = 0.0;
-            for (int a = 0; a < d; ++a) s += Jinv[r * d + a] * y[a];
-            Y[v][r] = s;
-          }
-        }
-        double* row = &A[(size_t)k * (nb - 1)];
-        std::fill(row, row + nb - 1, 0.0);
-        for (int q = 0; q < nq; ++q) {
-          double xi[3] = {0, 0, 0};
-          for (int v = 0; v < ns; ++v)
-            for (int r = 0; r < d; ++r) xi[r] += qlam[(size_t)q * ns + v] * Y[v][r];
-          basis_eval(d, M, xi, psi.data());
-          for (int l = 1; l < nb; ++l) row[l - 1] += qw[q] * psi[l];
-        }
-      }
+      stencil_rows(g, i, Jinv, list.data(), nl, M, qlam, qw, psi.data(), A.data());
       if (!pseudo_inverse(NE1, nb - 1, A.data(), P.data()))
         throw Error(CWENO_E_RANK, "rank-deficient least-squares system at cell " + std::to_string(i));
       for (int l = 0; l < nb - 1; ++l)   // device layout is k-major: row k*(nb-1) + l
@@ -312,6 +321,55 @@ void build_operators(const Geometry& g, const Stencils& st, int M, Operators& op
   });
   op.n_dropped = 0;
   for (int64_t x : dropped_per_cell) op.n_dropped += x;
+}
+
+}  // namespace cweno
+
+namespace cweno {
+
+void build_weno_operators(const Geometry& g, const WenoStencils& ws, int M, WenoOperators& op) {
+  const int d = g.d, ns = d + 1, nb = n_basis(M, d), NL = nb - 1, n_e = ws.n_e, NE1 = n_e - 1, n_s = ws.n_s;
+  if (n_s > 16) throw Error(CWENO_E_ARG, "too many WENO stencils");
+  op.n_s = n_s;
+  op.Np = (g.nc + 63) / 64 * 64;
+  const size_t Np = (size_t)op.Np;
+  op.pinv.assign((size_t)n_s * NE1 * NL * Np, 0.0);
+  op.gidx.assign((size_t)n_s * NE1 * Np, 0);
+  op.alive.assign(Np, 0);
+  std::vector<double> qlam, qw;
+  grundmann_moller(d, M, qlam, qw);
+  std::vector<int64_t> dropped(g.nc, 0);
+  parallel_for(g.nc, [&](int64_t b, int64_t e) {
+    std::vector<double> A((size_t)NE1 * NL), P((size_t)NL * NE1), psi(nb);
+    for (int64_t i = b; i < e; ++i) {
+      const double* Xi = &g.X[(size_t)i * ns * d];
+      double J[9], Jinv[9];
+      for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) J[r * d + c] = Xi[(c + 1) * d + r] - Xi[r];
+      if (!invert(d, J, Jinv)) throw Error(CWENO_E_MESH, "singular cell map at cell " + std::to_string(i));
+      uint16_t alive = 0;
+      for (int j = 0; j < n_s; ++j) {
+        const int32_t* S = &ws.cells[((size_t)i * n_s + j) * n_e];
+        if (S[0] < 0) {   // unfillable: dropped, gathers point at the cell itself
+          dropped[i]++;
+          for (int k = 0; k < NE1; ++k) op.gidx[((size_t)j * NE1 + k) * Np + i] = (int32_t)i;
+          continue;
+        }
+        stencil_rows(g, i, Jinv, S + 1, NE1, M, qlam, qw, psi.data(), A.data());
+        if (!pseudo_inverse(NE1, NL, A.data(), P.data()))
+          throw Error(CWENO_E_RANK, "rank-deficient WENO stencil " + std::to_string(j) + " at cell " +
+                                        std::to_string(i));
+        alive = (uint16_t)(alive | (1u << j));
+        for (int k = 0; k < NE1; ++k) {
+          op.gidx[((size_t)j * NE1 + k) * Np + i] = S[k + 1];
+          for (int l = 0; l < NL; ++l) op.pinv[(((size_t)j * NE1 + k) * NL + l) * Np + i] = P[(size_t)l * NE1 + k];
+        }
+      }
+      op.alive[i] = alive;
+    }
+  });
+  op.n_dropped = 0;
+  for (int64_t x : dropped) op.n_dropped += x;
 }
 
 }  // namespace cweno

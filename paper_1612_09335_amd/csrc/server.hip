@@ -474,6 +474,8 @@ cweno_status cweno_server_register(cweno_server* s, int dim, int64_t n_vertices,
   if (!s || !mesh_id) return fail(CWENO_E_ARG, "server and mesh_id must not be NULL");
   cweno_options o{};
   if (opt) o = *opt;
+  if (o.flags & (CWENO_FLAG_WENO | CWENO_FLAG_MOVING))
+    return fail(CWENO_E_ARG, "the server holds stored CWENO operators only (no WENO or moving meshes)");
   o.flags |= CWENO_FLAG_HOST_ONLY;
   o.ops = s->f32 ? CWENO_OPS_F32 : CWENO_OPS_F64;
   cweno_mesh* raw = nullptr;
