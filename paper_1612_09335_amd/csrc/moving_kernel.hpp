@@ -22,7 +22,7 @@
 //      cells' barycentres (the averages of a linear function), inverts the
 //      d x d system (eq. CWENO:Ps) and drops the sector if its 2-norm
 //      condition number, sigma_max(B) sigma_max(B^-1), exceeds 1e10;
-//   5. per block of VB variables, the differences dQ of the row cells are
+//   5. per pass of VB variables, the differences dQ of the row cells are
 //      reflected, R and Q^T dQ go to LDS, and one lane per variable solves
 //      R x = Q^T dQ, undoes the column scaling (P_opt, eq. CWENO:Popt with
 //      p_0 = Q_i), and forms the sector polynomials, P_0, the indicators, the
@@ -44,7 +44,12 @@
 
 namespace cweno {
 
-constexpr int kMoveVB = 4;         // variables reflected together
+// Variables reflected together (a pass): 2, 5 or 9; at most 5 where the
+// basis has more than 15 functions (the register budget of the 3-D M >= 3 rows).
+__host__ __device__ constexpr int move_vb_max(int D, int M) { return nbasis_c(M, D) - 1 <= 14 ? 9 : 5; }
+__host__ __device__ constexpr int move_vb(int D, int M, int nv) {
+  return nv <= 2 ? 2 : (nv <= 5 || move_vb_max(D, M) == 5) ? 5 : 9;
+}
 constexpr int kMoveThreads = 256;  // four waves per block
 
 template <typename T>
@@ -361,12 +366,11 @@ __device__ __forceinline__ void barycentre(const double (&X)[D + 1][D], double (
 
 // ---------------------------------------------------------------- kernel
 
-template <int D, int M, int SEG, int RPL, typename T>
+template <int D, int M, int SEG, int RPL, int VB, typename T>
 __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
   constexpr int NB = nbasis_c(M, D);
   constexpr int NL = NB - 1;
   constexpr int NS = D + 1;
-  constexpr int VB = kMoveVB;
   constexpr int CPW = 64 / SEG;                          // cells per wave
   constexpr int CPB = (kMoveThreads / 64) * CPW;         // cells per block
   constexpr int CH = 8;                                  // column sums in flight

@@ -23,17 +23,29 @@ typedef float real_t;
 namespace cweno {
 namespace {
 
-template <int SEG, int RPL>
-hipError_t launch_shape(const MParams<real_t>& p, hipStream_t s) {
-  if constexpr (move_shape_ok(CWENO_D, CWENO_M, SEG, RPL)) {
+template <int SEG, int RPL, int VB>
+hipError_t launch_vb(const MParams<real_t>& p, hipStream_t s) {
+  if constexpr (VB <= move_vb_max(CWENO_D, CWENO_M)) {
     constexpr int cpb = (kMoveThreads / 64) * (64 / SEG);
     const int64_t blocks = (p.nc + cpb - 1) / cpb;
-    hipLaunchKernelGGL((moving_kernel<CWENO_D, CWENO_M, SEG, RPL, real_t>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((moving_kernel<CWENO_D, CWENO_M, SEG, RPL, VB, real_t>), dim3((unsigned)blocks),
                        dim3(kMoveThreads), 0, s, p);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
   }
+}
+
+template <int SEG, int RPL>
+hipError_t launch_shape(const MParams<real_t>& p, hipStream_t s) {
+  if constexpr (move_shape_ok(CWENO_D, CWENO_M, SEG, RPL)) {
+    switch (move_vb(CWENO_D, CWENO_M, p.nv)) {
+      case 2: return launch_vb<SEG, RPL, 2>(p, s);
+      case 5: return launch_vb<SEG, RPL, 5>(p, s);
+      case 9: return launch_vb<SEG, RPL, 9>(p, s);
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
