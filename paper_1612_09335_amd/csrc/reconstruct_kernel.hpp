@@ -313,8 +313,10 @@ __device__ __forceinline__ void finish_variable(const KParams<T>& p, uint32_t io
 #pragma unroll
     for (int s = 1; s <= NS; ++s)
       if (lam[s] > T(0)) mmin = fmin(mmin, ms[s]);
+    // a dropped sector (lambda_s = 0) gets ratio 0: its sigma is 0, and
+    // m_min / eps raised to the power r would overflow in single precision
 #pragma unroll
-    for (int s = 0; s <= NS; ++s) om[s] = mmin * rcp_pos(ms[s]);
+    for (int s = 0; s <= NS; ++s) om[s] = lam[s] > T(0) ? mmin * rcp_pos(ms[s]) : T(0);
     powi<NS + 1, T>(om, p.r);
     T tot = T(0);
 #pragma unroll

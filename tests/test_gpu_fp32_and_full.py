@@ -45,6 +45,9 @@ CASES32 = {
     "tri24_M4_smooth_jump": (lambda: tri_mesh(24, 0.15, 8), 4, "smooth_jump", 0.0),
     "kuhn8_M3_blast": (lambda: kuhn_tet_mesh(8, 0.1, 9), 3, "euler3d_blast", 0.0),
     "kuhn6_M2_blast": (lambda: kuhn_tet_mesh(6, 0.1, 10), 2, "euler3d_blast", 0.0),
+    # bounded meshes: boundary cells have unfillable (dropped) sectors
+    "tri20_M3_bounded": (lambda: tri_mesh(20, 0.15, 12, periodic=False), 3, "smooth_jump", 0.0),
+    "kuhn5_M2_bounded": (lambda: kuhn_tet_mesh(5, 0.1, 13, periodic=False), 2, "euler3d_blast", 0.0),
 }
 
 
