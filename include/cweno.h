@@ -83,6 +83,9 @@ typedef enum {
                                          cweno_reconstruct_moving                                */
 #define CWENO_FLAG_WENO 16u           /* the classical unstructured WENO scheme instead of CWENO
                                          (see cweno_mesh_weno_tables)                            */
+#define CWENO_FLAG_DEVICE_OPERATORS 32u /* build the per-cell operators on the GPU (FP64) from the
+                                         host's stencils, in the same stored layout; central
+                                         stencils of at most 65 cells; not host-only, not WENO  */
 
 /* Reconstruction options.  A zero-initialised struct gives the defaults. */
 typedef struct {

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libcweno.so")
 F64, F32 = 0, 1
 OPS = {"f64": 0, "f32": 1, "both": 2, "none": 3}
 SECTOR_RULES = {"cone": 0, "face": 1}
-FLAG_HOST_ONLY, FLAG_SIGMA0_POPT, FLAG_LINEAR_WEIGHTS, FLAG_MOVING, FLAG_WENO = 1, 2, 4, 8, 16
+FLAG_HOST_ONLY, FLAG_SIGMA0_POPT, FLAG_LINEAR_WEIGHTS, FLAG_MOVING, FLAG_WENO, FLAG_DEVICE_OPERATORS = 1, 2, 4, 8, 16, 32
 
 STATUS = {0: "CWENO_OK", -1: "CWENO_E_ARG", -2: "CWENO_E_MESH", -3: "CWENO_E_STENCIL",
           -4: "CWENO_E_RANK", -5: "CWENO_E_PERIODIC", -6: "CWENO_E_NOMEM", -7: "CWENO_E_BUDGET",
@@ -139,7 +139,8 @@ class Mesh:
     def __init__(self, vertices, cells, degree: int, periodic=(0.0, 0.0, 0.0), stencil_factor: float = 0.0,
                  lambda0: float = 0.0, eps: float = 0.0, r: int = 0, ops: str = "f64",
                  sector_rule: str = "cone", sigma0_popt: bool = False, linear_weights: bool = False,
-                 host_only: bool = False, moving: bool = False, weno: bool = False, stream=None):
+                 host_only: bool = False, moving: bool = False, weno: bool = False,
+                 device_operators: bool = False, stream=None):
         V = np.ascontiguousarray(vertices, dtype=np.float64)
         C = np.ascontiguousarray(cells, dtype=np.int32)
         self.dim = int(V.shape[1])
@@ -155,7 +156,7 @@ class Mesh:
         o.sector_rule = SECTOR_RULES[sector_rule]
         o.flags = ((FLAG_HOST_ONLY if host_only else 0) | (FLAG_SIGMA0_POPT if sigma0_popt else 0)
                    | (FLAG_LINEAR_WEIGHTS if linear_weights else 0) | (FLAG_MOVING if moving else 0)
-                   | (FLAG_WENO if weno else 0))
+                   | (FLAG_WENO if weno else 0) | (FLAG_DEVICE_OPERATORS if device_operators else 0))
         self.weno = weno
         self.n_vertices = int(V.shape[0])
         self.moving = moving

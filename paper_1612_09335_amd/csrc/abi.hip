@@ -15,6 +15,7 @@
 #include "dispatch.hpp"
 #include "host.hpp"
 #include "mesh.hpp"
+#include "moving.hpp"
 #include "weno.hpp"
 
 namespace cweno_abi {
@@ -70,6 +71,110 @@ cweno_status upload(DevBuf& b, const void* src, size_t bytes, hipStream_t s, int
   // pageable source: wait before the host buffer may be released
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("hipStreamSynchronize failed: ") + hipGetErrorString(e));
+  return CWENO_OK;
+}
+
+cweno_status alloc_zero(DevBuf& b, size_t bytes, hipStream_t s, int64_t& total) {
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return fail(CWENO_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  total += (int64_t)bytes;
+  e = hipMemsetAsync(b.p, 0, bytes, s);
+  if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("hipMemsetAsync failed: ") + hipGetErrorString(e));
+  return CWENO_OK;
+}
+
+// Per-cell operators built on the device from the host's stencils: the
+// vertices, cells, stencils and quadrature rule go up (kept for a moving mesh,
+// freed otherwise), the assembly kernel writes pinv/binv/mask in the stored
+// layout, and its fault word turns into an error.
+cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int32_t* cells, int ops, hipStream_t s) {
+  const int dim = m->d;
+  int seg = 0, rpl = 0;
+  if (!cweno::move_shape(dim, m->M, m->n_e - 1, seg, rpl) || rpl != 1)
+    return fail(CWENO_E_ARG, "device operator assembly supports central stencils of at most 65 cells");
+  std::vector<double> lam, w, rule;
+  cweno::grundmann_moller(dim, m->M, lam, w);
+  const int nq = (int)w.size();
+  for (int k = 0; k < nq; ++k) {
+    for (int v = 0; v <= dim; ++v) rule.push_back(lam[(size_t)k * (dim + 1) + v]);
+    rule.push_back(w[k]);
+  }
+  int64_t scratch_bytes = 0;
+  DevBuf V, C, S0, SS, R, F;
+  const bool keep = (m->flags & CWENO_FLAG_MOVING) != 0;
+  cweno_status st;
+  // frees the scratch buffers, and the mesh tables unless a moving mesh took them
+  auto release = [&](bool tables) {
+    for (DevBuf* b : {&V, &F})
+      if (b->p) (void)hipFree(b->p);
+    if (tables)
+      for (DevBuf* b : {&C, &S0, &SS, &R})
+        if (b->p) (void)hipFree(b->p);
+  };
+  int64_t& tot = keep ? m->device_bytes : scratch_bytes;
+  if ((st = upload(V, vertices, (size_t)m->n_vertices * dim * 8, s, scratch_bytes)) ||
+      (st = upload(C, cells, (size_t)m->nc * (dim + 1) * 4, s, tot)) ||
+      (st = upload(S0, m->central.data(), m->central.size() * 4, s, tot)) ||
+      (st = upload(SS, m->sectors.data(), m->sectors.size() * 4, s, tot)) ||
+      (st = upload(R, rule.data(), rule.size() * 8, s, tot)) || (st = alloc_zero(F, 4, s, scratch_bytes))) {
+    release(true);
+    return st;
+  }
+  const size_t Np = (size_t)m->Np, NL = (size_t)(m->nb - 1), NE1 = (size_t)(m->n_e - 1);
+  const size_t nbinv = (size_t)(dim + 1) * dim * dim;
+  const bool f64 = ops == CWENO_OPS_F64 || ops == CWENO_OPS_BOTH, f32 = ops == CWENO_OPS_F32 || ops == CWENO_OPS_BOTH;
+  if ((f64 && ((st = alloc_zero(m->pinv64, NL * NE1 * Np * 8, s, m->device_bytes)) ||
+               (st = alloc_zero(m->binv64, nbinv * Np * 8, s, m->device_bytes)))) ||
+      (f32 && ((st = alloc_zero(m->pinv32, NL * NE1 * Np * 4, s, m->device_bytes)) ||
+               (st = alloc_zero(m->binv32, nbinv * Np * 4, s, m->device_bytes)))) ||
+      (st = alloc_zero(m->mask, Np, s, m->device_bytes))) {
+    release(true);
+    return st;
+  }
+  cweno::MParams<double> p{};
+  p.V = (const double*)V.p;
+  p.C = (const int32_t*)C.p;
+  p.S0 = (const int32_t*)S0.p;
+  p.SS = (const int32_t*)SS.p;
+  p.rule = (const double*)R.p;
+  p.fault = (int*)F.p;
+  p.pinv64 = (double*)m->pinv64.p;
+  p.pinv32 = (float*)m->pinv32.p;
+  p.binv64 = (double*)m->binv64.p;
+  p.binv32 = (float*)m->binv32.p;
+  p.mask = (uint8_t*)m->mask.p;
+  p.Np = m->Np;
+  for (int a = 0; a < 3; ++a) p.box[a] = m->box[a];
+  for (int t = 0; t < 5; ++t) p.lam[t] = m->lam[t];
+  p.eps = m->eps;
+  p.nc = m->nc;
+  p.n_e = m->n_e;
+  p.nq = nq;
+  p.r = m->r;
+  hipError_t e = cweno::launch_assemble(dim, m->M, p, seg, s);
+  int fault = 0;
+  std::vector<uint8_t> mask(m->nc);
+  if (e == hipSuccess) e = hipMemcpyAsync(&fault, F.p, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(mask.data(), m->mask.p, m->nc, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (keep) {
+    m->mvC = C;
+    m->mvS0 = S0;
+    m->mvSS = SS;
+    m->mvRule = R;
+    m->nq = nq;
+  }
+  release(!keep);
+  if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("operator assembly failed: ") + hipGetErrorString(e));
+  if (fault & 1) return fail(CWENO_E_MESH, "singular cell map (device operator assembly)");
+  if (fault & 2) return fail(CWENO_E_RANK, "rank-deficient least-squares system (device operator assembly)");
+  int64_t dropped = 0;
+  for (int64_t i = 0; i < m->nc; ++i) dropped += (dim + 1) - __builtin_popcount(mask[i]);
+  m->n_dropped = dropped;
   return CWENO_OK;
 }
 
@@ -189,6 +294,9 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
   if ((o.flags & CWENO_FLAG_MOVING) && (o.flags & CWENO_FLAG_HOST_ONLY))
     return fail(CWENO_E_ARG, "a moving mesh lives on the device; it cannot be host-only");
   const bool weno = (o.flags & CWENO_FLAG_WENO) != 0;
+  const bool dev_ops = (o.flags & CWENO_FLAG_DEVICE_OPERATORS) != 0;
+  if (dev_ops && ((o.flags & CWENO_FLAG_HOST_ONLY) || weno || o.ops == CWENO_OPS_NONE))
+    return fail(CWENO_E_ARG, "device operator assembly needs a device mesh with CWENO operators");
   if (weno && (o.flags & CWENO_FLAG_MOVING)) return fail(CWENO_E_ARG, "the WENO scheme has no moving-mesh form");
   if (weno && o.ops != CWENO_OPS_F64) return fail(CWENO_E_ARG, "the WENO scheme keeps FP64 operators only");
   if (weno && (o.flags & (CWENO_FLAG_SIGMA0_POPT | CWENO_FLAG_LINEAR_WEIGHTS)))
@@ -246,6 +354,8 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
         if ((ust = upload(m->wgidx, wop.gidx.data(), wop.gidx.size() * 4, s, m->device_bytes))) return ust;
         if ((ust = upload(m->walive, wop.alive.data(), wop.alive.size() * 2, s, m->device_bytes))) return ust;
       }
+    } else if (dev_ops) {
+      cweno::build_gather(g, st, degree, m->op);   // integer tables and Sigma; operators on the device
     } else if (o.ops != CWENO_OPS_NONE) {
       cweno::build_operators(g, st, degree, m->op);
     }
@@ -278,7 +388,7 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
         (uint64_t)(m->G + 1) * Np * 4u >= lim)
       return fail(CWENO_E_ARG, "mesh too large for 32-bit offsets within an operator block (split it)");
   }
-  if (!weno) m->n_dropped = m->op.n_dropped;
+  if (!weno && !dev_ops) m->n_dropped = m->op.n_dropped;
 
   if (!(o.flags & CWENO_FLAG_HOST_ONLY) && !weno) {
     hipStream_t s = (hipStream_t)hip_stream;
@@ -286,7 +396,13 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
     if (cweno_status cst = cweno_abi::configure_device_kernels()) return cst;
     const cweno::Operators& op = m->op;
     cweno_status st;
-    if (o.flags & CWENO_FLAG_MOVING) {
+    if (dev_ops) {
+      try {
+        if ((st = assemble_on_device(m.get(), vertices, cells, o.ops, s))) return st;
+      } catch (const std::bad_alloc&) {
+        return fail(CWENO_E_NOMEM, "host allocation failed during device assembly");
+      }
+    } else if (o.flags & CWENO_FLAG_MOVING) {
       // connectivity, stencils and the quadrature rule for the moving-mesh kernel
       std::vector<double> lam, w, rule;
       cweno::grundmann_moller(dim, degree, lam, w);
@@ -301,19 +417,23 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
       if ((st = upload(m->mvRule, rule.data(), rule.size() * 8, s, m->device_bytes))) return st;
     }
     if (o.ops == CWENO_OPS_F64 || o.ops == CWENO_OPS_BOTH) {
-      if ((st = upload(m->pinv64, op.pinv.data(), op.pinv.size() * 8, s, m->device_bytes))) return st;
-      if ((st = upload(m->binv64, op.binv.data(), op.binv.size() * 8, s, m->device_bytes))) return st;
+      if (!dev_ops) {
+        if ((st = upload(m->pinv64, op.pinv.data(), op.pinv.size() * 8, s, m->device_bytes))) return st;
+        if ((st = upload(m->binv64, op.binv.data(), op.binv.size() * 8, s, m->device_bytes))) return st;
+      }
       if ((st = upload(m->sigma64, op.sigma.data(), op.sigma.size() * 8, s, m->device_bytes))) return st;
     }
     if (o.ops == CWENO_OPS_F32 || o.ops == CWENO_OPS_BOTH) {
-      if ((st = upload_f32(m->pinv32, op.pinv, s, m->device_bytes))) return st;
-      if ((st = upload_f32(m->binv32, op.binv, s, m->device_bytes))) return st;
+      if (!dev_ops) {
+        if ((st = upload_f32(m->pinv32, op.pinv, s, m->device_bytes))) return st;
+        if ((st = upload_f32(m->binv32, op.binv, s, m->device_bytes))) return st;
+      }
       if ((st = upload_f32(m->sigma32, op.sigma, s, m->device_bytes))) return st;
     }
     if (o.ops != CWENO_OPS_NONE) {
       if ((st = upload(m->gidx, op.gidx.data(), op.gidx.size() * 4, s, m->device_bytes))) return st;
       if ((st = upload(m->secpos, op.secpos.data(), op.secpos.size(), s, m->device_bytes))) return st;
-      if ((st = upload(m->mask, op.mask.data(), op.mask.size(), s, m->device_bytes))) return st;
+      if (!dev_ops && (st = upload(m->mask, op.mask.data(), op.mask.size(), s, m->device_bytes))) return st;
       try {
         cweno::Halo h;
         cweno::build_halo(op, cweno::kHaloBlock, h);

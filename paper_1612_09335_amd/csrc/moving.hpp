@@ -40,6 +40,28 @@ CWENO_DECL_MOVE_ALL(f32, float)
 #undef CWENO_DECL_MOVE_ALL
 #undef CWENO_DECL_MOVE
 
+#define CWENO_DECL_ASM(d, m) hipError_t launch_assemble_d##d##_m##m(const MParams<double>& p, int seg, hipStream_t s);
+CWENO_DECL_ASM(2, 1) CWENO_DECL_ASM(2, 2) CWENO_DECL_ASM(2, 3) CWENO_DECL_ASM(2, 4)
+CWENO_DECL_ASM(3, 1) CWENO_DECL_ASM(3, 2) CWENO_DECL_ASM(3, 3) CWENO_DECL_ASM(3, 4)
+#undef CWENO_DECL_ASM
+
+// Operator assembly on the device: p's V, C, S0, SS and rule describe the mesh,
+// its pinv/binv/mask pointers receive the operators (one row per lane, so the
+// central stencil may hold at most 65 cells).
+inline hipError_t launch_assemble(int d, int m, const MParams<double>& p, int seg, hipStream_t s) {
+  switch (d * 10 + m) {
+    case 21: return launch_assemble_d2_m1(p, seg, s);
+    case 22: return launch_assemble_d2_m2(p, seg, s);
+    case 23: return launch_assemble_d2_m3(p, seg, s);
+    case 24: return launch_assemble_d2_m4(p, seg, s);
+    case 31: return launch_assemble_d3_m1(p, seg, s);
+    case 32: return launch_assemble_d3_m2(p, seg, s);
+    case 33: return launch_assemble_d3_m3(p, seg, s);
+    case 34: return launch_assemble_d3_m4(p, seg, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 #define CWENO_MOVE_CASES(tn)                                                             \
   switch (d * 10 + m) {                                                                  \
     case 21: return launch_moving_##tn##_d2_m1(p, seg, rpl, s);                          \

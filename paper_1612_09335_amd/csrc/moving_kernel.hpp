@@ -64,6 +64,14 @@ struct MParams {
   T* sig;                 // optional [nv][D+2][nc]
   T* om;                  // optional [nv][D+2][nc]
   int* fault;             // optional
+  // operator assembly (the VB = 0 form): the stored-operator layout, row stride Np;
+  // a NULL pointer skips that array
+  double* pinv64;
+  float* pinv32;
+  double* binv64;
+  float* binv32;
+  uint8_t* mask;
+  int64_t Np;
   double box[3];          // period per axis, 0 = none
   double lam[5];          // linear weights lambda_0 .. lambda_{D+1}
   double eps;
@@ -375,10 +383,12 @@ __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
   constexpr int CPB = (kMoveThreads / 64) * CPW;         // cells per block
   constexpr int CH = 8;                                  // column sums in flight
   static_assert(NL < SEG, "the rows of R lie in the first row slot of the segment's lanes");
-  // per-cell LDS record (doubles): P_opt of a block of variables, column
-  // scales, diagonal of R, reflector factors, sector inverses
-  constexpr int OP = 0, OSC = OP + VB * NL, ORD = OSC + NL, OTAU = ORD + NL, OBI = OTAU + NL,
-                OSZ = OBI + NS * D * D;
+  // per-cell LDS record (doubles): P_opt of a pass of variables (or, when
+  // assembling operators, the rows of R), column scales, diagonal of R,
+  // reflector factors, sector inverses
+  constexpr int OP = 0, OR = 0, OSC = OP + (VB > 0 ? VB * NL : NL * NL), ORD = OSC + NL, OTAU = ORD + NL,
+                OBI = OTAU + NL, OSZ = OBI + NS * D * D;
+  static_assert(VB > 0 || RPL == 1, "operator assembly keeps one row per lane");
   __shared__ double lds[CPB * OSZ];
   __shared__ int32_t ljs[CPB * NS * D];
 
@@ -619,6 +629,76 @@ __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
       if (!(fabs(L[ORD + k]) > 1e-12 * rmax)) fault |= 2;
   }
 
+  if constexpr (VB == 0) {
+    // 5'. operator assembly: the pseudo-inverse D^-1 R^-1 Q1^T and the sector
+    // inverses in the stored-operator layout (the same operators the host
+    // builder writes).  Rows of R to LDS for every row lane's back substitution.
+    if (row[0] < NL) {
+#pragma unroll
+      for (int c = 0; c < NL; ++c)
+        if (c > row[0]) L[OR + row[0] * NL + c] = A[0][c];
+    }
+    // row r of Q1 = H_0 ... H_{NL-1} [I; 0]; column c changes only under H_k, k <= c
+    double q1[NL];
+#pragma unroll
+    for (int c = 0; c < NL; ++c) q1[c] = row[0] == c ? 1.0 : 0.0;
+    auto orth = [&](auto kc) {
+      constexpr int k = NL - 1 - decltype(kc)::value;
+      const double tau = L[OTAU + k];
+      const double vk = row[0] >= k ? A[0][k] : 0.0;
+      auto chunk = [&](auto cc) {
+        constexpr int c0 = decltype(cc)::value * CH;
+        if constexpr (c0 + CH > k) {
+          double dot[CH];
+#pragma unroll
+          for (int u = 0; u < CH; ++u) {
+            const int c = c0 + u < NL ? c0 + u : NL - 1;
+            dot[u] = (c0 + u >= k && c0 + u < NL) ? vk * q1[c] : 0.0;
+          }
+          seg_sum<SEG, CH>(dot, k - c0 > 0 ? k - c0 : 0, NL - c0 < CH ? NL - c0 : CH);
+#pragma unroll
+          for (int u = 0; u < CH; ++u) {
+            const int c = c0 + u < NL ? c0 + u : NL - 1;
+            if (c0 + u >= k && c0 + u < NL) q1[c] = fma(-tau * dot[u], vk, q1[c]);
+          }
+        }
+      };
+      StaticFor<0, (NL + CH - 1) / CH>::run(chunk);
+    };
+    StaticFor<0, NL>::run(orth);
+    __syncthreads();
+    // column r of the pseudo-inverse: D^-1 R^-1 (row r of Q1)^T
+    if (valid && row[0] < NE1) {
+      auto back = [&](auto kc) {
+        constexpr int k = NL - 1 - decltype(kc)::value;
+        double s = q1[k];
+#pragma unroll
+        for (int c = k + 1; c < NL; ++c) s = fma(-L[OR + k * NL + c], q1[c], s);
+        q1[k] = s / L[ORD + k];
+      };
+      StaticFor<0, NL>::run(back);
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        const double x = q1[l] / L[OSC + l];
+        const int64_t at = ((int64_t)row[0] * NL + l) * p.Np + i;
+        if (p.pinv64) p.pinv64[at] = x;
+        if (p.pinv32) p.pinv32[at] = (float)x;
+      }
+    }
+    if (valid && sl < NS) {
+#pragma unroll
+      for (int l = 0; l < D; ++l)
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const int64_t at = (int64_t)((sl * D + l) * D + a) * p.Np + i;
+          const double x = L[OBI + (sl * D + l) * D + a];
+          if (p.binv64) p.binv64[at] = x;
+          if (p.binv32) p.binv32[at] = (float)x;
+        }
+    }
+    if (valid && sl == 0 && p.mask) p.mask[i] = (uint8_t)kmask;
+    (void)inv_l0;
+  } else {
   // 5. variable blocks
   for (int v0 = 0; v0 < p.nv; v0 += VB) {
     const int nvb = min(VB, p.nv - v0);
@@ -739,7 +819,7 @@ __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
         for (int s = 1; s <= NS; ++s)
           if (lam[s] > 0.0) mmin = fmin(mmin, ms[s]);
 #pragma unroll
-        for (int s = 0; s <= NS; ++s) om[s] = mmin / ms[s];
+        for (int s = 0; s <= NS; ++s) om[s] = lam[s] > 0.0 ? mmin / ms[s] : 0.0;
         powi<NS + 1, double>(om, p.r);
         double tot = 0.0;
 #pragma unroll
@@ -774,6 +854,7 @@ __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
       }
     }
     __syncthreads();
+  }
   }
   if (fault && valid && p.fault) atomicOr(p.fault, fault);
 }

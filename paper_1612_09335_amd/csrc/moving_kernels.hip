@@ -10,12 +10,16 @@
 #define CWENO_CAT4(a, b, c, d) a##b##c##d
 #define CWENO_MOVE_NAME(tn, d, m) CWENO_CAT4(launch_moving_, tn, _d##d, _m##m)
 #define CWENO_MOVE_FN(tn, d, m) CWENO_MOVE_NAME(tn, d, m)
+#define CWENO_ASM_NAME(d, m) CWENO_CAT4(launch_assemble, _d, d, _m##m)
+#define CWENO_ASM_FN(d, m) CWENO_ASM_NAME(d, m)
 #define f64 1
 #define f32 2
 #if CWENO_TN == 1
 typedef double real_t;
+#define CWENO_TN_IS_F64 1
 #else
 typedef float real_t;
+#define CWENO_TN_IS_F64 0
 #endif
 #undef f64
 #undef f32
@@ -49,6 +53,27 @@ hipError_t launch_shape(const MParams<real_t>& p, hipStream_t s) {
 }
 
 }  // namespace
+
+#if CWENO_TN_IS_F64
+// Operator assembly (one row per lane) for this (dimension, degree).
+hipError_t CWENO_ASM_FN(CWENO_D, CWENO_M)(const MParams<double>& p, int seg, hipStream_t s) {
+  auto go = [&](auto segc) -> hipError_t {
+    constexpr int SEG = decltype(segc)::value;
+    if constexpr (move_shape_ok(CWENO_D, CWENO_M, SEG, 1)) {
+      constexpr int cpb = (kMoveThreads / 64) * (64 / SEG);
+      const int64_t blocks = (p.nc + cpb - 1) / cpb;
+      hipLaunchKernelGGL((moving_kernel<CWENO_D, CWENO_M, SEG, 1, 0, double>), dim3((unsigned)blocks),
+                         dim3(kMoveThreads), 0, s, p);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  };
+  if (seg == 32) return go(std::integral_constant<int, 32>{});
+  if (seg == 64) return go(std::integral_constant<int, 64>{});
+  return hipErrorInvalidValue;
+}
+#endif
 
 hipError_t CWENO_MOVE_FN(CWENO_TN, CWENO_D, CWENO_M)(const MParams<real_t>& p, int seg, int rpl, hipStream_t s) {
   if (seg == 32 && rpl == 1) return launch_shape<32, 1>(p, s);
