@@ -254,8 +254,17 @@ def measure(torch, C, m, Q, M, factor, steps, warmup, label, d):
     lm = C.Mesh(m.vertices, m.cells, M, periodic=m.box, stencil_factor=factor, ops="both")
     t_pre = time.perf_counter() - t0
     log(f"{label}: precompute {t_pre:.2f} s, n_e={lm.n_e}, gather={lm.gather_len}, device bytes={lm.device_bytes}")
-    q64 = torch.tensor(Q, dtype=torch.float64, device=dev)
     res = {"precompute_s": t_pre, "n_e": lm.n_e, "mesh": lm}
+    if lm.n_e <= 65:
+        # the same operators assembled on the GPU from the host's stencils
+        t0 = time.perf_counter()
+        dm = C.Mesh(m.vertices, m.cells, M, periodic=m.box, stencil_factor=factor, ops="both",
+                    device_operators=True)
+        torch.cuda.synchronize()
+        res["precompute_device_operators_s"] = time.perf_counter() - t0
+        log(f"{label}: registration with operators assembled on the GPU {res['precompute_device_operators_s']:.2f} s")
+        del dm
+    q64 = torch.tensor(Q, dtype=torch.float64, device=dev)
     for tag, q, s in (("f64", q64, 8), ("f32", q64.float(), 4)):
         r = time_path(torch, lm, q, steps, warmup)
         got = r["out"][:, 0].cpu().numpy()
@@ -510,7 +519,8 @@ def main():
         r3 = measure(torch, C, m3, Q3, 3, 0.0, 20, 3, "kuhn64 M3", 3)
         extras["kuhn64_M3_nv5"] = {
             "workload": "3-D M=3, 1,572,864 jittered periodic Kuhn tetrahedra, n_e=60, 4 sectors, 5 variables",
-            "precompute_s": r3["precompute_s"]}
+            "precompute_s": r3["precompute_s"],
+            "precompute_device_operators_s": r3.get("precompute_device_operators_s")}
         for tag in ("f64", "f32"):
             extras["kuhn64_M3_nv5"][tag] = {k: r3[tag][k] for k in ("value", "ms_per_step", "latency_ms", "roofline",
                                                                    "variant", "flushed_ms", "flushed_frac")}
@@ -564,6 +574,7 @@ def main():
                  "dtype": "f32"},
         "cpu_baseline": cpu,
         "precompute_s": res["precompute_s"],
+        "precompute_device_operators_s": res.get("precompute_device_operators_s"),
         "extras": extras,
         "kernel_source_sha": kernel_source_hash(),
         "moving_kernel_source_sha": kernel_source_hash(MOVING_SRCS),
