@@ -819,7 +819,7 @@ __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
         for (int s = 1; s <= NS; ++s)
           if (lam[s] > 0.0) mmin = fmin(mmin, ms[s]);
 #pragma unroll
-        for (int s = 0; s <= NS; ++s) om[s] = lam[s] > 0.0 ? mmin / ms[s] : 0.0;
+        for (int s = 0; s <= NS; ++s) om[s] = mmin / ms[s];   // FP64: even (m_min / eps)^r stays finite
         powi<NS + 1, double>(om, p.r);
         double tot = 0.0;
 #pragma unroll
