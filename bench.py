@@ -143,10 +143,20 @@ def measure_evaluate(torch, C, lm, Q, M, d, steps):
         ms = time_loop(torch, lambda: lm.evaluate(pts, co, out=vals), steps, 3)
         alg = lm.n_cells * nv * s * (nb + len(P))
         gbs = alg / (ms * 1e-3) / 1e9
+        ms_two = time_loop(torch, lambda: (lm.reconstruct(q, out=co), lm.evaluate(pts, co, out=vals)), steps, 3)
+        ms_fused = time_loop(torch, lambda: lm.reconstruct_points(pts, q, out=vals), steps, 3)
+        fused_alg = (algorithmic_bytes_per_cell(d, M, lm.n_e, nv, s) + nv * s * (len(P) - nb)) * lm.n_cells
         out[tag] = {"ms_per_step": ms, "value": lm.n_cells * nv / (ms * 1e-3),
                     "roofline": dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
-                                     frac=gbs / HBM_PEAK_GBS, traffic=None, algorithmic_bytes_per_launch=alg)}
-        log(f"evaluate {tag}: {ms:.4f} ms, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
+                                     frac=gbs / HBM_PEAK_GBS, traffic=None, algorithmic_bytes_per_launch=alg),
+                    "reconstruct_then_evaluate_ms": ms_two, "fused_ms": ms_fused,
+                    "fused_roofline": dict(bound="hbm", achieved=fused_alg / (ms_fused * 1e-3) / 1e9,
+                                           peak=HBM_PEAK_GBS, unit="GB/s",
+                                           frac=fused_alg / (ms_fused * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                           algorithmic_bytes_per_launch=fused_alg)}
+        log(f"evaluate {tag}: {ms:.4f} ms, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak); "
+            f"reconstruct + evaluate {ms_two:.4f} ms, fused {ms_fused:.4f} ms "
+            f"({100 * out[tag]['fused_roofline']['frac']:.1f}% of HBM peak)")
         del q, co, vals
     return out
 

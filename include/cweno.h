@@ -269,6 +269,14 @@ cweno_status cweno_reconstruct_moving(const cweno_mesh* mesh, const double* vert
  *                       dtype; asynchronous on hip_stream; the point set must
  *                       have the mesh's dimension and degree; the buffers must
  *                       not overlap.  Errors: CWENO_E_ARG, CWENO_E_HIP.
+ * cweno_reconstruct_points  cweno_reconstruct and cweno_evaluate in one pass:
+ *                       the reconstruction kernel writes the polynomial's
+ *                       values at the point set (values [n_vars][n_points]
+ *                       [n_cells], dtype) instead of its coefficients, with
+ *                       the same bits as the two calls in sequence.  Needs a
+ *                       CWENO mesh with operators of dtype whose block halos
+ *                       fit in LDS; n_points * n_cells values of one variable
+ *                       below 4 GiB; q and values must not overlap.
  */
 typedef struct cweno_points cweno_points;
 cweno_status cweno_points_create(int dim, int degree, int n_points, const double* ref_points, cweno_points** out);
@@ -276,6 +284,8 @@ cweno_status cweno_points_basis(const cweno_points* points, double* phi);
 cweno_status cweno_points_destroy(cweno_points* points);
 cweno_status cweno_evaluate(const cweno_mesh* mesh, const cweno_points* points, int n_vars, cweno_dtype dtype,
                             const void* coeffs, void* values, void* hip_stream);
+cweno_status cweno_reconstruct_points(const cweno_mesh* mesh, const cweno_points* points, int n_vars,
+                                      cweno_dtype dtype, const void* q, void* values, void* hip_stream);
 
 /*
  * Classical unstructured WENO (CWENO_FLAG_WENO at cweno_mesh_create): the

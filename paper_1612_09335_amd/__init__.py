@@ -27,7 +27,8 @@ STATUS = {0: "CWENO_OK", -1: "CWENO_E_ARG", -2: "CWENO_E_MESH", -3: "CWENO_E_STE
 
 SYMBOLS = ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_mesh_tables",
            "cweno_mesh_operators", "cweno_mesh_weno_tables", "cweno_reconstruct", "cweno_reconstruct_moving", "cweno_points_create",
-           "cweno_points_basis", "cweno_points_destroy", "cweno_evaluate", "cweno_status_string",
+           "cweno_points_basis", "cweno_points_destroy", "cweno_evaluate", "cweno_reconstruct_points",
+           "cweno_status_string",
            "cweno_last_error",
            "cweno_abi_version", "cweno_num_variants", "cweno_mesh_set_variant", "cweno_mesh_get_variant",
            "cweno_mesh_tune", "cweno_batch_create", "cweno_batch_run", "cweno_batch_info", "cweno_batch_group",
@@ -76,6 +77,7 @@ def _load():
     lib.cweno_points_basis.argtypes = [vp, vp]
     lib.cweno_points_destroy.argtypes = [vp]
     lib.cweno_evaluate.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+    lib.cweno_reconstruct_points.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
     lib.cweno_mesh_set_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.cweno_mesh_get_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -289,6 +291,25 @@ class Mesh:
             stream = torch.cuda.current_stream(coeffs.device)
         _check(lib.cweno_evaluate(self._h, points._h, nv, dt, coeffs.data_ptr(), out.data_ptr(),
                                   _stream_ptr(stream)))
+        return out
+
+    def reconstruct_points(self, points, q, out=None, stream=None):
+        """cweno_reconstruct_points: q [n_vars, n_cells] -> values [n_vars, n_points, n_cells]."""
+        import torch
+        if not q.is_cuda or q.dim() != 2 or q.shape[1] != self.n_cells or not q.is_contiguous():
+            raise ValueError("q must be a contiguous CUDA tensor [n_vars, n_cells]")
+        dt = {torch.float64: F64, torch.float32: F32}.get(q.dtype)
+        if dt is None:
+            raise ValueError("q must be float64 or float32")
+        shape = (q.shape[0], points.n_points, self.n_cells)
+        if out is None:
+            out = torch.empty(shape, dtype=q.dtype, device=q.device)
+        elif tuple(out.shape) != shape or out.dtype != q.dtype or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous {q.dtype} tensor {shape}")
+        if stream is None:
+            stream = torch.cuda.current_stream(q.device)
+        _check(lib.cweno_reconstruct_points(self._h, points._h, q.shape[0], dt, q.data_ptr(), out.data_ptr(),
+                                            _stream_ptr(stream)))
         return out
 
     # ---------------------------------------------------------------- variants

@@ -45,6 +45,7 @@ inline int pick_vb(int D, int M, int n, bool f32) {
 // dynamic-LDS limit of the unit's halo kernels (outside any stream capture).
 #define CWENO_DECLARE(TN, T, D, M)                                                                    \
   hipError_t launch_##TN##_d##D##_m##M(const KParams<T>& p, int vb, int k, hipStream_t s);           \
+  hipError_t launch_points_##TN##_d##D##_m##M(const KParams<T>& p, int vb, hipStream_t s);           \
   hipError_t launch_batch_##TN##_d##D##_m##M(const KParams<T>* table, const BatchItem* items, int n, \
                                              int grid, size_t lds, int vb, int k, hipStream_t s);    \
   hipError_t configure_##TN##_d##D##_m##M();
@@ -76,6 +77,23 @@ inline hipError_t launch_batch(int D, int M, const KParams<T>* table, const Batc
                                size_t lds, int vb, int k, hipStream_t s) {
 #define CWENO_CASE(TN, DD, MM) \
   if (D == DD && M == MM) return launch_batch_##TN##_d##DD##_m##MM(table, items, n, grid, lds, vb, k, s);
+  if constexpr (sizeof(T) == 8) {
+    CWENO_CASE(f64, 2, 1) CWENO_CASE(f64, 2, 2) CWENO_CASE(f64, 2, 3) CWENO_CASE(f64, 2, 4)
+    CWENO_CASE(f64, 3, 1) CWENO_CASE(f64, 3, 2) CWENO_CASE(f64, 3, 3) CWENO_CASE(f64, 3, 4)
+  } else {
+    CWENO_CASE(f32, 2, 1) CWENO_CASE(f32, 2, 2) CWENO_CASE(f32, 2, 3) CWENO_CASE(f32, 2, 4)
+    CWENO_CASE(f32, 3, 1) CWENO_CASE(f32, 3, 2) CWENO_CASE(f32, 3, 3) CWENO_CASE(f32, 3, 4)
+  }
+#undef CWENO_CASE
+  return hipErrorInvalidValue;
+}
+
+// The halo kernel (chunk 1, halo unroll 4) writing the reconstruction's values
+// at a point set (p.phi, p.pv, p.npts) instead of its coefficients.
+template <typename T>
+inline hipError_t launch_points(int D, int M, const KParams<T>& p, int vb, hipStream_t s) {
+#define CWENO_CASE(TN, DD, MM) \
+  if (D == DD && M == MM) return launch_points_##TN##_d##DD##_m##MM(p, vb, s);
   if constexpr (sizeof(T) == 8) {
     CWENO_CASE(f64, 2, 1) CWENO_CASE(f64, 2, 2) CWENO_CASE(f64, 2, 3) CWENO_CASE(f64, 2, 4)
     CWENO_CASE(f64, 3, 1) CWENO_CASE(f64, 3, 2) CWENO_CASE(f64, 3, 3) CWENO_CASE(f64, 3, 4)

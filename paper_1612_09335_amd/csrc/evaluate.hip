@@ -21,6 +21,7 @@
 
 #include "cweno.h"
 #include "host.hpp"
+#include "dispatch.hpp"
 #include "mesh.hpp"
 #include "reconstruct_kernel.hpp"
 
@@ -143,6 +144,52 @@ cweno_status cweno_points_destroy(cweno_points* p) {
 cweno_status cweno_points_basis(const cweno_points* p, double* phi) {
   if (!p || !phi) return fail(CWENO_E_ARG, "points and phi are required");
   std::copy(p->phi.begin(), p->phi.end(), phi);
+  return CWENO_OK;
+}
+
+cweno_status cweno_reconstruct_points(const cweno_mesh* m, const cweno_points* pts, int n_vars, cweno_dtype dtype,
+                                      const void* q, void* values, void* hip_stream) {
+  if (!m || !pts) return fail(CWENO_E_ARG, "mesh and points are required");
+  if (pts->d != m->d || pts->M != m->M) return fail(CWENO_E_ARG, "point set built for another dimension or degree");
+  if (n_vars < 1) return fail(CWENO_E_ARG, "n_vars must be >= 1");
+  if (!q || !values) return fail(CWENO_E_ARG, "q and values must be device pointers");
+  if (dtype != CWENO_F64 && dtype != CWENO_F32) return fail(CWENO_E_ARG, "bad dtype");
+  if (m->n_s > 0) return fail(CWENO_E_ARG, "a WENO mesh has no fused point values (reconstruct, then evaluate)");
+  const bool f32 = dtype == CWENO_F32;
+  if ((f32 && !m->pinv32.p) || (!f32 && !m->pinv64.p))
+    return fail(CWENO_E_ARG, "the mesh holds no operators of this precision");
+  if (m->maxH <= 0) return fail(CWENO_E_ARG, "fused point values need the LDS-halo kernel, which this mesh cannot use");
+  const uint64_t es = f32 ? 4 : 8, cells = (uint64_t)m->nc * (uint64_t)n_vars;
+  if ((uint64_t)pts->n * (uint64_t)m->nc * es >= (uint64_t(1) << 32) ||
+      (uint64_t)m->nc * (uint64_t)m->nb * es >= (uint64_t(1) << 32))
+    return fail(CWENO_E_ARG, "too many cells or points for 32-bit offsets within one variable's values");
+  if (overlap(q, cells * es, values, cells * (uint64_t)pts->n * es))
+    return fail(CWENO_E_ARG, "q and values must not overlap");
+  hipStream_t s = (hipStream_t)hip_stream;
+  for (int v0 = 0; v0 < n_vars;) {
+    int vb = cweno::pick_vb(m->d, m->M, n_vars - v0, f32);
+    // the block halo of vb variables and a column of nb-1 coefficients per thread must fit in LDS
+    const int64_t col = ((int64_t)(m->nb - 1) * cweno::kHaloBlock + (int64_t)pts->n * m->nb) * (int64_t)es;
+    while (vb > 1 && (int64_t)m->maxH * vb * (int64_t)es + col > cweno::kMaxLds) vb = cweno::pick_vb(m->d, m->M, vb - 1, f32);
+    if ((int64_t)m->maxH * vb * (int64_t)es + col > cweno::kMaxLds)
+      return fail(CWENO_E_ARG, "the block halos of this mesh leave no room for the fused point values");
+    hipError_t e;
+    if (f32) {
+      cweno::KParams<float> p = cweno_abi::make_params<float>(m, q, nullptr, nullptr, nullptr, v0);
+      p.phi = (const float*)pts->phi32.p;
+      p.pv = (float*)values;
+      p.npts = pts->n;
+      e = cweno::launch_points<float>(m->d, m->M, p, vb, s);
+    } else {
+      cweno::KParams<double> p = cweno_abi::make_params<double>(m, q, nullptr, nullptr, nullptr, v0);
+      p.phi = (const double*)pts->phi64.p;
+      p.pv = (double*)values;
+      p.npts = pts->n;
+      e = cweno::launch_points<double>(m->d, m->M, p, vb, s);
+    }
+    if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    v0 += vb;
+  }
   return CWENO_OK;
 }
 

@@ -26,6 +26,7 @@
 namespace cweno {
 
 constexpr int kHaloBlock = 256;   // cells (and threads) per workgroup; fixed by the host's halo lists
+static_assert(kHaloBlock == kHaloBlockLanes, "one cell per thread of a halo workgroup");
 
 template <int NL, int KC, typename T>
 __device__ __forceinline__ void load_rows(T (&r)[KC][NL], const T* pinv, int64_t Np, int NE1, int k0,
@@ -73,7 +74,7 @@ __device__ __forceinline__ void fma_chunk(T (&acc)[NL][VB], const T (&r)[KC][NL]
 
 // One block b of kHaloBlock consecutive cells of the mesh described by p, with
 // lq as the block's LDS halo.  Every thread of the workgroup returns normally.
-template <int D, int M, int VB, int KC, int HU, typename T>
+template <int D, int M, int VB, int KC, int HU, typename T, bool PTS = false>
 __device__ __forceinline__ void halo_block(const KParams<T>& p, int64_t b, T* lq) {
   constexpr int NB = nbasis_c(M, D);
   constexpr int NL = NB - 1;
@@ -90,6 +91,13 @@ __device__ __forceinline__ void halo_block(const KParams<T>& p, int64_t b, T* lq
   const rsrc_t rl = make_rsrc(p.lidx, (uint32_t)(p.G + 1) * lrow);
   const rsrc_t rq = make_rsrc(p.q + (int64_t)p.v0 * qs, (uint32_t)VB * (uint32_t)qs * (uint32_t)sizeof(T));
   const uint32_t qrow = (uint32_t)qs * (uint32_t)sizeof(T);
+
+  // fused point values: the basis values at the points go to LDS with the halo
+  // (read by every lane at the same address; written before the barrier)
+  T* const lphi = PTS ? lq + (size_t)p.maxH * VB + (size_t)NL * kHaloBlock : nullptr;
+  if constexpr (PTS) {
+    for (int t = tid; t < p.npts * NB; t += kHaloBlock) lphi[t] = p.phi[t];
+  }
 
   // stage the block's halo averages, HU entries per thread at a time
   const int h0 = p.hoff[b], hn = p.hoff[b + 1] - h0;
@@ -167,16 +175,17 @@ __device__ __forceinline__ void halo_block(const KParams<T>& p, int64_t b, T* lq
       T po[NL];
 #pragma unroll
       for (int l = 0; l < NL; ++l) po[l] = acc[l][v];
-      finish_variable<D, M, T>(p, io, v, qi, po, lam, inv_l0, dqs, bv);
+      finish_variable<D, M, T, PTS>(p, io, v, qi, po, lam, inv_l0, dqs, bv,
+                                    PTS ? lq + (size_t)p.maxH * VB + tid : nullptr, lphi);
     }
   }
 }
 
-template <int D, int M, int VB, int KC, int HU, typename T>
+template <int D, int M, int VB, int KC, int HU, typename T, bool PTS = false>
 __global__ __launch_bounds__(kHaloBlock) void reconstruct_halo_kernel(KParams<T> p, CWENO_ARRAY_PARAMS(T)) {
   CWENO_BIND_ARRAYS(p);
   extern __shared__ __align__(16) unsigned char halo_raw[];
-  halo_block<D, M, VB, KC, HU, T>(p, xcd_block(blockIdx.x, gridDim.x), reinterpret_cast<T*>(halo_raw));
+  halo_block<D, M, VB, KC, HU, T, PTS>(p, xcd_block(blockIdx.x, gridDim.x), reinterpret_cast<T*>(halo_raw));
 }
 
 // Work item of the batched kernel: block `block` of the mesh (and variable

@@ -14,6 +14,8 @@
 #define CWENO_BATCH_NAME(tn, d, m) CWENO_CAT4(launch_batch_, tn, _d##d, _m##m)
 #define CWENO_BATCH_FN(tn, d, m) CWENO_BATCH_NAME(tn, d, m)
 #define CWENO_CONF_NAME(tn, d, m) CWENO_CAT4(configure_, tn, _d##d, _m##m)
+#define CWENO_PTS_NAME(tn, d, m) CWENO_CAT4(launch_points_, tn, _d##d, _m##m)
+#define CWENO_PTS_FN(tn, d, m) CWENO_PTS_NAME(tn, d, m)
 #define CWENO_CONF_FN(tn, d, m) CWENO_CONF_NAME(tn, d, m)
 #define f64 1
 #define f32 2
@@ -27,6 +29,23 @@ typedef float real_t;
 
 namespace cweno {
 namespace {
+
+// Fused point values: the halo kernel with chunk 1 and halo unroll 4.
+template <int VB>
+hipError_t launch_points_t(const KParams<real_t>& p, hipStream_t s) {
+  if constexpr (vb_allowed(CWENO_D, CWENO_M, VB, sizeof(real_t) == 4)) {
+    const int64_t blocks = (p.nc + kHaloBlock - 1) / kHaloBlock;
+    // block halo, a column of nb-1 blended coefficients per thread, the basis values at the points
+    constexpr int NB = nbasis_c(CWENO_M, CWENO_D);
+    const size_t lds = ((size_t)p.maxH * VB + (size_t)(NB - 1) * kHaloBlock + (size_t)p.npts * NB) * sizeof(real_t);
+    if (p.maxH <= 0 || lds > (size_t)kMaxLds || !p.phi || !p.pv || p.npts < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((reconstruct_halo_kernel<CWENO_D, CWENO_M, VB, 1, 4, real_t, true>), dim3((unsigned)blocks),
+                       dim3(kHaloBlock), lds, s, p, CWENO_ARRAY_ARGS(p));
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
 
 template <int VB, int KC>
 hipError_t launch_direct(const KParams<real_t>& p, hipStream_t s) {
@@ -76,6 +95,9 @@ hipError_t configure_t() {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     if (e == hipSuccess)
       e = hipFuncSetAttribute((const void*)reconstruct_batch_kernel<CWENO_D, CWENO_M, VB, KC, HU, real_t>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (e == hipSuccess && KC == 1 && HU == 4)
+      e = hipFuncSetAttribute((const void*)reconstruct_halo_kernel<CWENO_D, CWENO_M, VB, 1, 4, real_t, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     return e;
   } else {
@@ -130,6 +152,18 @@ hipError_t CWENO_FN(CWENO_TN, CWENO_D, CWENO_M)(const KParams<real_t>& p, int vb
     case 4: return launch_variant<4>(p, k, s);
     case 5: return launch_variant<5>(p, k, s);
     case 9: return launch_variant<9>(p, k, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t CWENO_PTS_FN(CWENO_TN, CWENO_D, CWENO_M)(const KParams<real_t>& p, int vb, hipStream_t s) {
+  switch (vb) {
+    case 1: return launch_points_t<1>(p, s);
+    case 2: return launch_points_t<2>(p, s);
+    case 3: return launch_points_t<3>(p, s);
+    case 4: return launch_points_t<4>(p, s);
+    case 5: return launch_points_t<5>(p, s);
+    case 9: return launch_points_t<9>(p, s);
     default: return hipErrorInvalidValue;
   }
 }

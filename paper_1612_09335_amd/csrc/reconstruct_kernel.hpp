@@ -43,6 +43,7 @@
 namespace cweno {
 
 constexpr int kThreads = 256;
+constexpr int kHaloBlockLanes = 256;   // threads of a halo-kernel workgroup (one cell each)
 
 __host__ __device__ constexpr int nbasis_c(int M, int D) {
   return D == 2 ? (M + 1) * (M + 2) / 2 : (M + 1) * (M + 2) * (M + 3) / 6;
@@ -74,6 +75,11 @@ struct KParams {
   int linear_w;    // omega := lambda
   T lam[5];        // lambda_0 .. lambda_{d+1}
   T eps;
+  // fused point values (the PTS kernels): basis values [npts][NB] and
+  // values [nv][npts][nc] written instead of the coefficients
+  const T* phi;
+  T* pv;
+  int npts;
 };
 
 // Every array also reaches a kernel as an argument of its own, marked
@@ -250,10 +256,11 @@ __device__ __forceinline__ void load_binv(const T* binv, int64_t Np, uint32_t io
 // dqs[s][a] = Q_{j^s(a)} - Q_i.  lam holds the cell's linear weights
 // (normalised), inv_l0 = 1 / lam[0].  io is the lane's byte offset of its
 // cell in an operator or coefficient row.
-template <int D, int M, typename T>
+template <int D, int M, typename T, bool PTS = false>
 __device__ __forceinline__ void finish_variable(const KParams<T>& p, uint32_t io, int v, T qi,
                                                 T (&po)[nbasis_c(M, D) - 1], const T (&lam)[D + 2], T inv_l0,
-                                                const T (&dqs)[D + 1][D], const T (&bv)[D + 1][D][D]) {
+                                                const T (&dqs)[D + 1][D], const T (&bv)[D + 1][D][D],
+                                                T* lw = nullptr, const T* lphi = nullptr) {
   constexpr int NB = nbasis_c(M, D);
   constexpr int NL = NB - 1;
   constexpr int NS = D + 1;
@@ -329,17 +336,45 @@ __device__ __forceinline__ void finish_variable(const KParams<T>& p, uint32_t io
     for (int s = 0; s <= NS; ++s) om[s] *= inv;
   }
   // blend: w = omega_0 P_0 + sum_s omega_s P_s; coefficient 0 is Q_i itself
-  const rsrc_t ro = make_rsrc(p.out + (int64_t)(p.v0 + v) * NB * qs, NB * crow);
-  bst(ro, qi, io, 0u);
   const T c0 = om[0] * inv_l0;
+  if constexpr (!PTS) {
+    const rsrc_t ro = make_rsrc(p.out + (int64_t)(p.v0 + v) * NB * qs, NB * crow);
+    bst(ro, qi, io, 0u);
 #pragma unroll
-  for (int l = 0; l < NL; ++l) {
-    T x = c0 * po[l];
-    if (l < D) {
+    for (int l = 0; l < NL; ++l) {
+      T x = c0 * po[l];
+      if (l < D) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) x = fma(om[s + 1], ps[s][l < D ? l : 0], x);
+        for (int s = 0; s < NS; ++s) x = fma(om[s + 1], ps[s][l < D ? l : 0], x);
+      }
+      bst(ro, x, io, (uint32_t)(l + 1) * crow);
     }
-    bst(ro, x, io, (uint32_t)(l + 1) * crow);
+  } else {
+    // the polynomial's values at the point set instead of its coefficients,
+    // summed in the order of the evaluation kernel (same bits); the blended
+    // coefficients wait in the lane's LDS column lw[l * kHaloBlock] so that
+    // they hold no registers while the other variables' sums are live, and
+    // the basis values at the points come from the LDS copy lphi
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      T x = c0 * po[l];
+      if (l < D) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) x = fma(om[s + 1], ps[s][l < D ? l : 0], x);
+      }
+      lw[l * kHaloBlockLanes] = x;
+    }
+    const rsrc_t rp = make_rsrc(p.pv + (int64_t)(p.v0 + v) * p.npts * qs, (uint32_t)p.npts * crow);
+    T w[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) w[l] = lw[l * kHaloBlockLanes];
+    for (int q = 0; q < p.npts; ++q) {
+      const T* f = lphi + q * NB;
+      T x = fma(f[0], qi, T(0));
+#pragma unroll
+      for (int l = 0; l < NL; ++l) x = fma(f[l + 1], w[l], x);
+      bst(rp, x, io, (uint32_t)q * crow);
+    }
   }
   if (p.sig) {
     const rsrc_t rs = make_rsrc(p.sig + (int64_t)(p.v0 + v) * (NS + 1) * qs, (NS + 1) * crow);

@@ -103,3 +103,47 @@ def test_evaluate_arguments():
     v = lm.evaluate(pts, co)
     torch.cuda.synchronize()
     assert torch.count_nonzero(v).item() == 0
+
+
+FUSED = [("tri12_M3_nv9", lambda: tri_mesh(12, 0.15, 640), 3, 9), ("tri11_M2_nv7", lambda: tri_mesh(11, 0.15, 641), 2, 7),
+         ("tri10_M4_nv3", lambda: tri_mesh(10, 0.15, 642), 4, 3), ("kuhn5_M3_nv5", lambda: kuhn_tet_mesh(5, 0.1, 643), 3, 5),
+         ("kuhn4_M2_nv11", lambda: kuhn_tet_mesh(4, 0.1, 644), 2, 11),
+         ("tri12_M3_bounded_nv4", lambda: tri_mesh(12, 0.15, 645, periodic=False), 3, 4)]
+
+
+@pytest.mark.parametrize("name,mk,M,nv", FUSED)
+def test_fused_point_values_equal_reconstruct_then_evaluate(name, mk, M, nv):
+    """cweno_reconstruct_points gives the bits of cweno_reconstruct followed by
+    cweno_evaluate (same blend, same sums in the same order)."""
+    torch = torch_cuda()
+    import paper_1612_09335_amd as C
+    m = mk()
+    d = m.dim
+    print(f"[gpu evaluate] fused {name}: {m.n_cells} cells", flush=True)
+    lm = C.Mesh(m.vertices, m.cells, M, periodic=m.box, ops="both")
+    pts = C.Points(d, M, _ref_points(d, 650 + M))
+    rng = np.random.default_rng(651)
+    Q = rng.normal(size=(nv, m.n_cells)) + 3.0 * (rng.random((1, m.n_cells)) < 0.3)
+    for tdt in (torch.float64, torch.float32):
+        q = torch.tensor(Q, dtype=tdt, device="cuda:0")
+        two = lm.evaluate(pts, lm.reconstruct(q))
+        fused = torch.full_like(two, float("nan"))
+        lm.reconstruct_points(pts, q, out=fused)
+        torch.cuda.synchronize()
+        assert torch.equal(fused, two), (name, tdt)
+
+
+def test_fused_point_values_refusals():
+    torch = torch_cuda()
+    import paper_1612_09335_amd as C
+    m = tri_mesh(16, 0.15, 660)
+    pts = C.Points(2, 2, [[0.2, 0.3]])
+    w = C.Mesh(m.vertices, m.cells, 2, periodic=m.box, weno=True)
+    q = torch.zeros((2, w.n_cells), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(C.CwenoError):
+        w.reconstruct_points(pts, q)                            # WENO mesh
+    f64 = C.Mesh(m.vertices, m.cells, 2, periodic=m.box, ops="f64")
+    with pytest.raises(C.CwenoError):
+        f64.reconstruct_points(pts, q.float())                  # no FP32 operators
+    with pytest.raises(C.CwenoError):
+        f64.reconstruct_points(C.Points(2, 3, [[0.2, 0.3]]), q)  # point set of another degree
