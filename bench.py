@@ -447,9 +447,26 @@ def cpu_baseline(m, Q, degree, factor, budget_s):
             o.reconstruct_cell(int(cells[done]), Q)
             done += 1
         dt = time.perf_counter() - t0
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return dict(value=done * Q.shape[0] / dt, unit="cells·vars/s", cores=1, kind="oracle",
                 sample=f"{done} random cells of the benchmark mesh (all {Q.shape[0]} variables), "
-                       f"one thread, {dt:.1f} s; oracle set-up (face adjacency) excluded")
+                       f"one thread, {dt:.1f} s; oracle set-up (face adjacency) excluded",
+                host_cores_available=len(os.sched_getaffinity(0)), cpu_model=model)
+
+
+def measured_copy_gbs(torch):
+    """Bandwidth of a plain 1 GiB device-to-device copy (bytes read + written per second)."""
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    ms = time_loop(torch, lambda: b.copy_(a), 20, 3)
+    return 2 * a.numel() * 8 / (ms * 1e-3) / 1e9
 
 
 def main():
@@ -495,8 +512,12 @@ def main():
     Q = workload_fields(m, "mhd2d", SEED)
     nv = Q.shape[0]
     res = measure(torch, C, m, Q, M, factor, args.steps, args.warmup, "tri512 M3", d)
+    copy_gbs = measured_copy_gbs(torch)
+    log(f"plain device copy: {copy_gbs:.0f} GB/s")
     for tag in ("f64", "f32"):
         res[tag]["roofline"]["traffic"] = load_traffic(tag)
+        res[tag]["roofline"]["measured_copy_gbs"] = copy_gbs
+        res[tag]["roofline"]["frac_of_measured_copy"] = res[tag]["roofline"]["achieved"] / copy_gbs
 
     extras = {}
     try:

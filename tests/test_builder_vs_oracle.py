@@ -128,3 +128,24 @@ def test_similarity_transform_keeps_tables_and_operators():
         Pb, Bb, _ = b.operators(i)
         np.testing.assert_allclose(Pb, Pa, atol=1e-11 * np.abs(Pa).max())
         np.testing.assert_allclose(Bb, Ba, atol=1e-11 * np.abs(Ba).max())
+
+
+def test_renumbering_permutes_tables():
+    """Renumbering cells and vertices (each cell's vertex order kept) permutes
+    the central and sector stencils and the host operators, nothing else."""
+    m = kuhn_tet_mesh(5, 0.1, 71)
+    rng = np.random.default_rng(72)
+    pc = rng.permutation(m.n_cells)
+    pv = rng.permutation(m.n_vertices)
+    inv_v = np.empty_like(pv)
+    inv_v[pv] = np.arange(len(pv))
+    a = C.Mesh(m.vertices, m.cells, 2, periodic=m.box, host_only=True)
+    b = C.Mesh(m.vertices[pv], inv_v[m.cells[pc]].astype(np.int32), 2, periodic=m.box, host_only=True)
+    ta, tb = a.tables(), b.tables()
+    assert np.array_equal(pc[tb["stencil"]], ta["stencil"][pc])
+    sb = tb["sectors"]
+    assert np.array_equal(np.where(sb >= 0, pc[np.maximum(sb, 0)], -1), ta["sectors"][pc])
+    for k in (0, 17, m.n_cells - 1):
+        Pa, Ba, _ = a.operators(int(pc[k]))
+        Pb, Bb, _ = b.operators(k)
+        assert np.array_equal(Pa, Pb) and np.array_equal(Ba, Bb)
