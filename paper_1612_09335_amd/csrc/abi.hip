@@ -104,7 +104,8 @@ cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int
     rule.push_back(w[k]);
   }
   int64_t scratch_bytes = 0;
-  DevBuf V, C, S0, SS, R, F;
+  DevBuf V, C, S0, SS, SP, R, F;
+  const std::vector<uint8_t> sp = cweno_abi::sector_rows(dim, m->nc, m->n_e, m->central, m->sectors);
   const bool keep = (m->flags & CWENO_FLAG_MOVING) != 0;
   cweno_status st;
   // frees the scratch buffers, and the mesh tables unless a moving mesh took them
@@ -112,7 +113,7 @@ cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int
     for (DevBuf* b : {&V, &F})
       if (b->p) (void)hipFree(b->p);
     if (tables)
-      for (DevBuf* b : {&C, &S0, &SS, &R})
+      for (DevBuf* b : {&C, &S0, &SS, &SP, &R})
         if (b->p) (void)hipFree(b->p);
   };
   int64_t& tot = keep ? m->device_bytes : scratch_bytes;
@@ -120,6 +121,7 @@ cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int
       (st = upload(C, cells, (size_t)m->nc * (dim + 1) * 4, s, tot)) ||
       (st = upload(S0, m->central.data(), m->central.size() * 4, s, tot)) ||
       (st = upload(SS, m->sectors.data(), m->sectors.size() * 4, s, tot)) ||
+      (st = upload(SP, sp.data(), sp.size(), s, tot)) ||
       (st = upload(R, rule.data(), rule.size() * 8, s, tot)) || (st = alloc_zero(F, 4, s, scratch_bytes))) {
     release(true);
     return st;
@@ -140,6 +142,7 @@ cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int
   p.C = (const int32_t*)C.p;
   p.S0 = (const int32_t*)S0.p;
   p.SS = (const int32_t*)SS.p;
+  p.SP = (const uint8_t*)SP.p;
   p.rule = (const double*)R.p;
   p.fault = (int*)F.p;
   p.pinv64 = (double*)m->pinv64.p;
@@ -165,6 +168,7 @@ cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int
     m->mvC = C;
     m->mvS0 = S0;
     m->mvSS = SS;
+    m->mvSP = SP;
     m->mvRule = R;
     m->nq = nq;
   }
@@ -414,6 +418,8 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
       if ((st = upload(m->mvC, cells, (size_t)n_cells * (dim + 1) * 4, s, m->device_bytes))) return st;
       if ((st = upload(m->mvS0, m->central.data(), m->central.size() * 4, s, m->device_bytes))) return st;
       if ((st = upload(m->mvSS, m->sectors.data(), m->sectors.size() * 4, s, m->device_bytes))) return st;
+      const std::vector<uint8_t> sp = cweno_abi::sector_rows(dim, n_cells, m->n_e, m->central, m->sectors);
+      if ((st = upload(m->mvSP, sp.data(), sp.size(), s, m->device_bytes))) return st;
       if ((st = upload(m->mvRule, rule.data(), rule.size() * 8, s, m->device_bytes))) return st;
     }
     if (o.ops == CWENO_OPS_F64 || o.ops == CWENO_OPS_BOTH) {

@@ -28,6 +28,29 @@ inline bool overlap(const void* a, uint64_t na, const void* b, uint64_t nb) {
   return x < y + nb && y < x + na;
 }
 
+// For every sector cell of every cell, its row in the central stencil (its
+// position there minus one) or 255 if it is not in it: [nc][d+1][d]
+// (the moving-mesh kernel reads such cells' barycentres from its row lanes).
+inline std::vector<uint8_t> sector_rows(int d, int64_t nc, int n_e, const std::vector<int32_t>& central,
+                                        const std::vector<int32_t>& sectors) {
+  const int ns = d + 1;
+  std::vector<uint8_t> out((size_t)nc * ns * d, 255);
+  for (int64_t i = 0; i < nc; ++i) {
+    const int32_t* S0 = &central[(size_t)i * n_e];
+    for (int s = 0; s < ns; ++s) {
+      const int32_t* sec = &sectors[((size_t)i * ns + s) * ns];
+      if (sec[0] < 0) continue;
+      for (int a = 0; a < d; ++a)
+        for (int k = 1; k < n_e && k <= 255; ++k)
+          if (S0[k] == sec[a + 1]) {
+            out[((size_t)i * ns + s) * d + a] = (uint8_t)(k - 1);
+            break;
+          }
+    }
+  }
+  return out;
+}
+
 // Raise the dynamic-LDS limit of every halo kernel once per device (before
 // any launch, so that launches may later be captured into graphs).
 cweno_status configure_device_kernels();
@@ -52,7 +75,7 @@ struct cweno_mesh {
   int maxH = 0;
   // moving meshes: cell vertex ids, central and sector stencils (cell-major),
   // quadrature rule [nq][d+2]
-  cweno_abi::DevBuf mvC, mvS0, mvSS, mvRule;
+  cweno_abi::DevBuf mvC, mvS0, mvSS, mvSP, mvRule;
   int nq = 0;
   int64_t n_vertices = 0;
   // classical WENO meshes (n_s > 0): stencil tables [nc][n_s][n_e] on the host,
@@ -69,7 +92,7 @@ struct cweno_mesh {
   ~cweno_mesh() {
     if (!owns_device) return;
     for (cweno_abi::DevBuf* b : {&pinv64, &binv64, &sigma64, &pinv32, &binv32, &sigma32, &gidx, &secpos, &mask, &halo,
-                                 &hoff, &lidx, &mvC, &mvS0, &mvSS, &mvRule, &wpinv, &wgidx, &walive})
+                                 &hoff, &lidx, &mvC, &mvS0, &mvSS, &mvSP, &mvRule, &wpinv, &wgidx, &walive})
       if (b->p) (void)hipFree(b->p);
   }
 };

@@ -20,6 +20,7 @@ cweno::MParams<T> moving_params(const cweno_mesh* m, const double* vertices, int
   p.C = (const int32_t*)m->mvC.p;
   p.S0 = (const int32_t*)m->mvS0.p;
   p.SS = (const int32_t*)m->mvSS.p;
+  p.SP = (const uint8_t*)m->mvSP.p;
   p.rule = (const double*)m->mvRule.p;
   p.q = (const T*)q;
   p.out = (T*)coeffs;

@@ -58,6 +58,7 @@ struct MParams {
   const int32_t* C;       // [nc][D+1] vertex ids of each cell
   const int32_t* S0;      // [nc][n_e] central stencil, the cell first
   const int32_t* SS;      // [nc][D+1][D+1] sector stencils, the cell first; first entry < 0: not filled
+  const uint8_t* SP;      // [nc][D+1][D] row of each sector cell in the central stencil (its position - 1), 255: not in it
   const double* rule;     // [nq][D+2] quadrature: barycentric coordinates, then the weight (weights sum 1)
   const T* q;             // [nv][nc]
   T* out;                 // [nv][NB][nc]
@@ -385,9 +386,10 @@ __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
   static_assert(NL < SEG, "the rows of R lie in the first row slot of the segment's lanes");
   // per-cell LDS record (doubles): P_opt of a pass of variables (or, when
   // assembling operators, the rows of R), column scales, diagonal of R,
-  // reflector factors, sector inverses
+  // reflector factors, sector inverses, each row cell's barycentre in the
+  // cell's reference frame
   constexpr int OP = 0, OR = 0, OSC = OP + (VB > 0 ? VB * NL : NL * NL), ORD = OSC + NL, OTAU = ORD + NL,
-                OBI = OTAU + NL, OSZ = OBI + NS * D * D;
+                OBI = OTAU + NL, OXI = OBI + NS * D * D, OSZ = OXI + SEG * RPL * D;
   static_assert(VB > 0 || RPL == 1, "operator assembly keeps one row per lane");
   __shared__ double lds[CPB * OSZ];
   __shared__ int32_t ljs[CPB * NS * D];
@@ -441,6 +443,18 @@ __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
       for (int a = 0; a < D; ++a) {
         const double dc = cj[a] - ci[a];
         sh[a] = min_image_d(dc, p.box[a]) - dc;
+      }
+      {   // the barycentre in the cell's frame, for the sector lanes
+        double y[D];
+#pragma unroll
+        for (int b = 0; b < D; ++b) y[b] = ci[b] + min_image_d(cj[b] - ci[b], p.box[b]) - X0[b];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          double t2 = 0.0;
+#pragma unroll
+          for (int b = 0; b < D; ++b) t2 = fma(Jinv[r][b], y[b], t2);
+          L[OXI + row[t] * D + r] = t2;
+        }
       }
 #pragma unroll
       for (int v = 0; v < NS; ++v) {
@@ -553,6 +567,7 @@ __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
   };
   StaticFor<0, NL>::run(qr_step);
 
+  __syncthreads();   // the row cells' barycentres in LDS
   // 4. sectors: lane s of the segment builds and inverts sector s
   bool kept = false;
   if (sl < NS) {
@@ -568,20 +583,28 @@ __global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
     for (int a = 0; a < D; ++a) sj[a] = (int32_t)ic;
     if (ss[0] >= 0) {
       double B[D][D];
+      const uint8_t* sp = p.SP + (ic * NS + s) * D;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         sj[a] = ss[a + 1];
-        double X[NS][D], cj[D], y[D], xi[D];
-        cell_vertices<D>(p, sj[a], X);
-        barycentre<D>(X, cj);
+        double xi[D];
+        const int pos = sp[a];
+        if (pos != 255) {   // a central-stencil cell: its row lane left the barycentre in LDS
 #pragma unroll
-        for (int b = 0; b < D; ++b) y[b] = ci[b] + min_image_d(cj[b] - ci[b], p.box[b]) - X0[b];
+          for (int r = 0; r < D; ++r) xi[r] = L[OXI + pos * D + r];
+        } else {
+          double X[NS][D], cj[D], y[D];
+          cell_vertices<D>(p, sj[a], X);
+          barycentre<D>(X, cj);
 #pragma unroll
-        for (int r = 0; r < D; ++r) {
-          double t = 0.0;
+          for (int b = 0; b < D; ++b) y[b] = ci[b] + min_image_d(cj[b] - ci[b], p.box[b]) - X0[b];
 #pragma unroll
-          for (int b = 0; b < D; ++b) t = fma(Jinv[r][b], y[b], t);
-          xi[r] = t;
+          for (int r = 0; r < D; ++r) {
+            double t = 0.0;
+#pragma unroll
+            for (int b = 0; b < D; ++b) t = fma(Jinv[r][b], y[b], t);
+            xi[r] = t;
+          }
         }
         linear_basis<D>(xi, B[a]);
       }
