@@ -52,6 +52,16 @@ __host__ __device__ constexpr int move_vb(int D, int M, int nv) {
 }
 constexpr int kMoveThreads = 256;  // four waves per block
 
+// Waves per SIMD the register allocation must leave room for.  The 3-D
+// degree-3 kernels with one stencil row per lane need 200-218 registers on
+// their own (two waves); bounded to 168 they run three waves with a few
+// spills, which measured 9% faster.  The kernels with two rows per lane and
+// the 3-D degree-4 ones need all 256 and would spill heavily; the others fit
+// three or four waves unbounded.
+__host__ __device__ constexpr int move_min_waves(int D, int M, int RPL) {
+  return D == 3 && M == 3 && RPL == 1 ? 3 : 1;
+}
+
 template <typename T>
 struct MParams {
   const double* V;        // [n_vertices][D] positions for this call
@@ -376,7 +386,8 @@ __device__ __forceinline__ void barycentre(const double (&X)[D + 1][D], double (
 // ---------------------------------------------------------------- kernel
 
 template <int D, int M, int SEG, int RPL, int VB, typename T>
-__global__ __launch_bounds__(kMoveThreads) void moving_kernel(MParams<T> p) {
+__global__ __launch_bounds__(kMoveThreads) __attribute__((amdgpu_waves_per_eu(move_min_waves(D, M, RPL))))
+void moving_kernel(MParams<T> p) {
   constexpr int NB = nbasis_c(M, D);
   constexpr int NL = NB - 1;
   constexpr int NS = D + 1;
