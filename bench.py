@@ -170,7 +170,7 @@ def measure_weno(torch, C, m, Q, M, d, steps, cweno_ms, cweno_n_e):
     nb, n_e, n_s = lm.n_basis, lm.n_e, 1 + 2 * (d + 1)
     nl, ne1 = nb - 1, n_e - 1
     vbmax = 4 if nl <= 9 else (2 if nl <= 19 else 1)
-    passes = -(-nv // vbmax)
+    passes = -(-nv // (8 * vbmax))        # up to 8 lanes per cell, vbmax variables each, per pass
     weno_entries = n_s * nl * ne1
     cweno_entries = nl * (cweno_n_e - 1) + (d + 1) * d * d
     alg = (8 * weno_entries + 4 * n_s * ne1 + 2 + nv * 8 * (1 + nb)) * m.n_cells

@@ -301,7 +301,10 @@ cweno_status cweno_reconstruct_points(const cweno_mesh* mesh, const cweno_points
  * w = sum omega~ P / sum omega~.  An unfillable stencil is dropped.  Such a
  * mesh keeps FP64 operators only (ops must be CWENO_OPS_F64; no moving form,
  * no CWENO-only flags); cweno_reconstruct runs the WENO kernel (FP64, sigma and
- * omega must be NULL); it cannot join a batch or a server.
+ * omega must be NULL); it cannot join a batch or a server.  Creation fails
+ * with CWENO_E_ARG if the stencils of 64 consecutive cells reference more than
+ * 8192 distinct cells (the kernel stages that halo in LDS); a reconstruction
+ * takes as many variables per pass as the largest such halo leaves room for.
  *
  * cweno_mesh_weno_tables  *n_stencils = n_s; stencils (may be NULL) receives
  *                         the host table [n_cells][n_s][n_e] int32 (the cell

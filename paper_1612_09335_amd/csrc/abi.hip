@@ -225,7 +225,9 @@ cweno_status reconstruct_weno(const cweno_mesh* m, int n_vars, cweno_dtype dtype
   p.q = (const double*)q;
   p.out = (double*)coeffs;
   p.pinv = (const double*)m->wpinv.p;
-  p.gidx = (const int32_t*)m->wgidx.p;
+  p.lidx = (const uint16_t*)m->wlidx.p;
+  p.halo = (const int32_t*)m->whalo.p;
+  p.hoff = (const int32_t*)m->whoff.p;
   p.alive = (const uint16_t*)m->walive.p;
   p.lam0 = m->lam[0];
   p.lams = (1.0 - m->lam[0]) / (m->n_s - 1);
@@ -235,13 +237,22 @@ cweno_status reconstruct_weno(const cweno_mesh* m, int n_vars, cweno_dtype dtype
   p.NE1 = m->n_e - 1;
   p.n_s = m->n_s;
   p.r = m->r;
+  // a pass takes up to kWenoMaxGroup * vbmax variables (G lanes per cell with
+  // VB each, VB as even as the count allows), and no more than the LDS holds
+  // for the longest block halo
   const int vbmax = cweno::weno_vb_max(m->d, m->M);
+  const int lds_vars = (int)(cweno::kWenoMaxLds / ((size_t)m->wmaxH * sizeof(double)));
+  const int per_pass = std::min(cweno::kWenoMaxGroup * vbmax, lds_vars);
   for (int v0 = 0; v0 < n_vars;) {
-    const int vb = std::min(vbmax, n_vars - v0);
+    const int n = std::min(n_vars - v0, per_pass);
+    const int g0 = (n + vbmax - 1) / vbmax;
+    const int vb = (n + g0 - 1) / g0;
     p.v0 = v0;
-    const hipError_t e = cweno::launch_weno(m->d, m->M, p, vb, (hipStream_t)hip_stream);
+    p.v1 = v0 + n;
+    p.G = (n + vb - 1) / vb;
+    const hipError_t e = cweno::launch_weno(m->d, m->M, p, vb, m->wmaxH, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
-    v0 += vb;
+    v0 += n;
   }
   return CWENO_OK;
 }
@@ -350,13 +361,28 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
       m->n_s = ws.n_s;
       m->weno_cells.swap(ws.cells);
       m->n_dropped = wop.n_dropped;
+      // halos of the kernel's blocks over the gather lists of all stencils
+      cweno::Halo wh;
+      {
+        cweno::Operators gl;
+        gl.nc = n_cells;
+        gl.Np = wop.Np;
+        gl.G = m->n_s * (m->n_e - 1);
+        gl.gidx.swap(wop.gidx);
+        cweno::build_halo(gl, cweno::kWenoBlockCells, wh);
+      }
+      m->wmaxH = wh.max_len;
+      if ((size_t)m->wmaxH * sizeof(double) > cweno::kWenoMaxLds)
+        return fail(CWENO_E_ARG, "WENO block halo too large for LDS");
       if (!(o.flags & CWENO_FLAG_HOST_ONLY)) {
         hipStream_t s = (hipStream_t)hip_stream;
         if (hipGetDevice(&m->device) != hipSuccess) return fail(CWENO_E_HIP, "no HIP device");
         cweno_status ust;
         if ((ust = upload(m->wpinv, wop.pinv.data(), wop.pinv.size() * 8, s, m->device_bytes))) return ust;
-        if ((ust = upload(m->wgidx, wop.gidx.data(), wop.gidx.size() * 4, s, m->device_bytes))) return ust;
         if ((ust = upload(m->walive, wop.alive.data(), wop.alive.size() * 2, s, m->device_bytes))) return ust;
+        if ((ust = upload(m->wlidx, wh.lidx.data(), wh.lidx.size() * 2, s, m->device_bytes))) return ust;
+        if ((ust = upload(m->whalo, wh.cells.data(), wh.cells.size() * 4, s, m->device_bytes))) return ust;
+        if ((ust = upload(m->whoff, wh.offset.data(), wh.offset.size() * 4, s, m->device_bytes))) return ust;
       }
     } else if (dev_ops) {
       cweno::build_gather(g, st, degree, m->op);   // integer tables and Sigma; operators on the device

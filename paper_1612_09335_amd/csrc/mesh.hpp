@@ -78,11 +78,13 @@ struct cweno_mesh {
   cweno_abi::DevBuf mvC, mvS0, mvSS, mvSP, mvRule;
   int nq = 0;
   int64_t n_vertices = 0;
-  // classical WENO meshes (n_s > 0): stencil tables [nc][n_s][n_e] on the host,
-  // operators, gathers and kept-stencil bits on the device
+  // classical WENO meshes (n_s > 0): stencil tables [nc][n_s][n_e] on the host;
+  // operators, kept-stencil bits and the halos of blocks of 64 cells (cells,
+  // offsets, 16-bit positions of every stencil entry) on the device
   int n_s = 0;
   std::vector<int32_t> weno_cells;
-  cweno_abi::DevBuf wpinv, wgidx, walive;
+  cweno_abi::DevBuf wpinv, walive, whalo, whoff, wlidx;
+  int wmaxH = 0;
   double box[3] = {0, 0, 0};
   int64_t device_bytes = 0;
   bool owns_device = true;   // false: the device buffers point into memory owned elsewhere (a server arena)
@@ -92,7 +94,7 @@ struct cweno_mesh {
   ~cweno_mesh() {
     if (!owns_device) return;
     for (cweno_abi::DevBuf* b : {&pinv64, &binv64, &sigma64, &pinv32, &binv32, &sigma32, &gidx, &secpos, &mask, &halo,
-                                 &hoff, &lidx, &mvC, &mvS0, &mvSS, &mvSP, &mvRule, &wpinv, &wgidx, &walive})
+                                 &hoff, &lidx, &mvC, &mvS0, &mvSS, &mvSP, &mvRule, &wpinv, &walive, &whalo, &whoff, &wlidx})
       if (b->p) (void)hipFree(b->p);
   }
 };

@@ -6,11 +6,22 @@
 // with the universal Sigma; omega~_j = lambda_j / (sigma_j + eps)^r;
 // w = sum_j omega~_j P_j / sum_j omega~_j (eqs. weights, weights2).
 //
-// One lane per cell, VB variables per pass.  Every stencil's polynomial is
-// needed whole before its weight is known, so a pass keeps the polynomial
-// being formed and the weighted running sum: 2 (nb-1) VB accumulators, which
-// limits VB to 4 / 2 / 1 for nb-1 up to 9 / 19 / 34.  Operator rows stream
-// once per pass with a non-temporal policy; neighbour averages are gathered.
+// A workgroup takes kWenoBlockCells consecutive cells with a group of G lanes
+// per cell (G <= 8), each lane reconstructing VB of the pass's variables.  It
+// first copies the averages of its halo -- the sorted unique cells its
+// stencils reference, listed on the host -- for every variable of the pass
+// into LDS, then reads every stencil difference from LDS through 16-bit
+// halo positions: the 1 + 2(d+1) stencils of a cell overlap, and neighbouring
+// cells share most of them, so each average comes from HBM once per block.
+// Every stencil's polynomial is needed whole before its weight is known, so a
+// lane keeps the polynomial being formed and the weighted running sum:
+// 2 (nb-1) VB accumulators, which limits VB to 4 / 2 / 1 for nb-1 up to
+// 9 / 19 / 34.  The lanes of a group load the same operator entries in the
+// same instruction, so the wave fetches each entry once per pass; operator
+// rows stream with a non-temporal policy.
+//
+// LDS layout: [halo cell][variable of the pass], the variables of a cell
+// together.
 #include <hip/hip_runtime.h>
 
 #include "mesh.hpp"
@@ -20,21 +31,40 @@
 namespace cweno {
 
 template <int D, int M, int VB>
-__global__ __launch_bounds__(kThreads) void weno_kernel(WParams p, const double* __restrict__ q,
-                                                        double* __restrict__ out, const double* __restrict__ pinv,
-                                                        const int32_t* __restrict__ gidx,
-                                                        const uint16_t* __restrict__ alive) {
+__global__ __launch_bounds__(kWenoBlockCells * kWenoMaxGroup) void weno_kernel(WParams p) {
   constexpr int NB = nbasis_c(M, D);
   constexpr int NL = NB - 1;
-  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
-  if (i >= p.nc) return;
+  extern __shared__ double lq[];
+  const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
+  const int G = p.G, nvp = p.v1 - p.v0;
   const int64_t nc = p.nc, Np = p.Np;
+  const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+
+  // stage the block's halo, cell-fastest so that runs of consecutive cells
+  // read consecutive addresses
+  const int h0 = p.hoff[b], hn = p.hoff[b + 1] - h0;
+  for (int t = tid; t < hn * nvp; t += nthr) {
+    const int v = t / hn, hc = t - v * hn;
+    lq[hc * nvp + v] = p.q[(int64_t)(p.v0 + v) * nc + p.halo[h0 + hc]];
+  }
+  __syncthreads();
+
+  const int cw = tid / G, sub = tid - cw * G;
+  const int64_t i = b * kWenoBlockCells + cw;
+  if (i >= nc) return;
+  const int vofs = sub * VB;                            // this lane's first variable within the pass
+  const int nvl = min(VB, nvp - vofs);                  // and how many it owns
+  if (nvl <= 0) return;
   const int NE1 = p.NE1, n_s = p.n_s;
-  const double* qb = q + (int64_t)p.v0 * nc;
+  const uint16_t* li = p.lidx + i;
+  int vv[VB];                                           // LDS column of each variable (the last repeated)
+#pragma unroll
+  for (int v = 0; v < VB; ++v) vv[v] = vofs + min(v, nvl - 1);
+  const double* ls = lq + (int)li[(int64_t)n_s * NE1 * Np] * nvp;
   double qi[VB];
 #pragma unroll
-  for (int v = 0; v < VB; ++v) qi[v] = qb[v * nc + i];
-  const unsigned am = alive[i];
+  for (int v = 0; v < VB; ++v) qi[v] = ls[vv[v]];
+  const unsigned am = p.alive[i];
   double lsum = 0.0;
   for (int j = 0; j < n_s; ++j)
     if ((am >> j) & 1u) lsum += j == 0 ? p.lam0 : p.lams;
@@ -53,13 +83,13 @@ __global__ __launch_bounds__(kThreads) void weno_kernel(WParams p, const double*
     for (int l = 0; l < NL; ++l)
 #pragma unroll
       for (int v = 0; v < VB; ++v) acc[l][v] = 0.0;
-    const double* pj = pinv + (int64_t)j * NE1 * NL * Np + i;
-    const int32_t* gj = gidx + (int64_t)j * NE1 * Np + i;
+    const double* pj = p.pinv + (int64_t)j * NE1 * NL * Np + i;
+    const uint16_t* lj16 = li + (int64_t)j * NE1 * Np;
     for (int k = 0; k < NE1; ++k) {
-      const int64_t c = gj[(int64_t)k * Np];
+      const double* lh = lq + (int)lj16[(int64_t)k * Np] * nvp;
       double dq[VB];
 #pragma unroll
-      for (int v = 0; v < VB; ++v) dq[v] = qb[v * nc + c] - qi[v];
+      for (int v = 0; v < VB; ++v) dq[v] = lh[vv[v]] - qi[v];
       const double* pk = pj + (int64_t)k * NL * Np;
 #pragma unroll
       for (int l = 0; l < NL; ++l) {
@@ -83,7 +113,8 @@ __global__ __launch_bounds__(kThreads) void weno_kernel(WParams p, const double*
   }
 #pragma unroll
   for (int v = 0; v < VB; ++v) {
-    double* o = out + (int64_t)(p.v0 + v) * NB * nc + i;
+    if (v >= nvl) break;
+    double* o = p.out + (int64_t)(p.v0 + vofs + v) * NB * nc + i;
     o[0] = qi[v];
     const double iw = 1.0 / ws[v];
 #pragma unroll
@@ -94,14 +125,18 @@ __global__ __launch_bounds__(kThreads) void weno_kernel(WParams p, const double*
 namespace {
 
 template <int D, int M>
-hipError_t launch_dm(const WParams& p, int vb, hipStream_t s) {
-  const unsigned blocks = (unsigned)((p.nc + kThreads - 1) / kThreads);
+hipError_t launch_dm(const WParams& p, int vb, int max_halo, hipStream_t s) {
+  const int nvp = p.v1 - p.v0;
+  if (p.G < 1 || p.G > kWenoMaxGroup || nvp < 1 || nvp > p.G * vb) return hipErrorInvalidValue;
+  const size_t lds = (size_t)max_halo * (size_t)nvp * sizeof(double);
+  if (lds > kWenoMaxLds) return hipErrorInvalidValue;
+  const unsigned blocks = (unsigned)((p.nc + kWenoBlockCells - 1) / kWenoBlockCells);
+  const unsigned threads = (unsigned)(kWenoBlockCells * p.G);
   switch (vb) {
 #define CWENO_WENO_VB(V)                                                                                         \
   case V:                                                                                                        \
     if constexpr (V <= weno_vb_max(D, M)) {                                                                      \
-      hipLaunchKernelGGL((weno_kernel<D, M, V>), dim3(blocks), dim3(kThreads), 0, s, p, p.q, p.out, p.pinv,      \
-                         p.gidx, p.alive);                                                                       \
+      hipLaunchKernelGGL((weno_kernel<D, M, V>), dim3(blocks), dim3(threads), lds, s, p);                         \
       return hipGetLastError();                                                                                  \
     }                                                                                                            \
     break;
@@ -113,16 +148,16 @@ hipError_t launch_dm(const WParams& p, int vb, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_weno(int d, int M, const WParams& p, int vb, hipStream_t s) {
+hipError_t launch_weno(int d, int M, const WParams& p, int vb, int max_halo, hipStream_t s) {
   switch (d * 10 + M) {
-    case 21: return launch_dm<2, 1>(p, vb, s);
-    case 22: return launch_dm<2, 2>(p, vb, s);
-    case 23: return launch_dm<2, 3>(p, vb, s);
-    case 24: return launch_dm<2, 4>(p, vb, s);
-    case 31: return launch_dm<3, 1>(p, vb, s);
-    case 32: return launch_dm<3, 2>(p, vb, s);
-    case 33: return launch_dm<3, 3>(p, vb, s);
-    case 34: return launch_dm<3, 4>(p, vb, s);
+    case 21: return launch_dm<2, 1>(p, vb, max_halo, s);
+    case 22: return launch_dm<2, 2>(p, vb, max_halo, s);
+    case 23: return launch_dm<2, 3>(p, vb, max_halo, s);
+    case 24: return launch_dm<2, 4>(p, vb, max_halo, s);
+    case 31: return launch_dm<3, 1>(p, vb, max_halo, s);
+    case 32: return launch_dm<3, 2>(p, vb, max_halo, s);
+    case 33: return launch_dm<3, 3>(p, vb, max_halo, s);
+    case 34: return launch_dm<3, 4>(p, vb, max_halo, s);
   }
   return hipErrorInvalidValue;
 }
