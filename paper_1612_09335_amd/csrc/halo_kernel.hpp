@@ -92,12 +92,6 @@ __device__ __forceinline__ void halo_block(const KParams<T>& p, int64_t b, T* lq
   const rsrc_t rq = make_rsrc(p.q + (int64_t)p.v0 * qs, (uint32_t)VB * (uint32_t)qs * (uint32_t)sizeof(T));
   const uint32_t qrow = (uint32_t)qs * (uint32_t)sizeof(T);
 
-  // fused point values: the basis values at the points go to LDS with the halo
-  // (read by every lane at the same address; written before the barrier)
-  T* const lphi = PTS ? lq + (size_t)p.maxH * VB + (size_t)NL * kHaloBlock : nullptr;
-  if constexpr (PTS) {
-    for (int t = tid; t < p.npts * NB; t += kHaloBlock) lphi[t] = p.phi[t];
-  }
 
   // stage the block's halo averages, HU entries per thread at a time
   const int h0 = p.hoff[b], hn = p.hoff[b + 1] - h0;
@@ -176,7 +170,7 @@ __device__ __forceinline__ void halo_block(const KParams<T>& p, int64_t b, T* lq
 #pragma unroll
       for (int l = 0; l < NL; ++l) po[l] = acc[l][v];
       finish_variable<D, M, T, PTS>(p, io, v, qi, po, lam, inv_l0, dqs, bv,
-                                    PTS ? lq + (size_t)p.maxH * VB + tid : nullptr, lphi);
+                                    PTS ? lq + (size_t)p.maxH * VB + tid : nullptr);
     }
   }
 }

@@ -35,9 +35,9 @@ template <int VB>
 hipError_t launch_points_t(const KParams<real_t>& p, hipStream_t s) {
   if constexpr (vb_allowed(CWENO_D, CWENO_M, VB, sizeof(real_t) == 4)) {
     const int64_t blocks = (p.nc + kHaloBlock - 1) / kHaloBlock;
-    // block halo, a column of nb-1 blended coefficients per thread, the basis values at the points
+    // block halo and a column of nb-1 blended coefficients per thread
     constexpr int NB = nbasis_c(CWENO_M, CWENO_D);
-    const size_t lds = ((size_t)p.maxH * VB + (size_t)(NB - 1) * kHaloBlock + (size_t)p.npts * NB) * sizeof(real_t);
+    const size_t lds = ((size_t)p.maxH * VB + (size_t)(NB - 1) * kHaloBlock) * sizeof(real_t);
     if (p.maxH <= 0 || lds > (size_t)kMaxLds || !p.phi || !p.pv || p.npts < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL((reconstruct_halo_kernel<CWENO_D, CWENO_M, VB, 1, 4, real_t, true>), dim3((unsigned)blocks),
                        dim3(kHaloBlock), lds, s, p, CWENO_ARRAY_ARGS(p));

@@ -260,7 +260,7 @@ template <int D, int M, typename T, bool PTS = false>
 __device__ __forceinline__ void finish_variable(const KParams<T>& p, uint32_t io, int v, T qi,
                                                 T (&po)[nbasis_c(M, D) - 1], const T (&lam)[D + 2], T inv_l0,
                                                 const T (&dqs)[D + 1][D], const T (&bv)[D + 1][D][D],
-                                                T* lw = nullptr, const T* lphi = nullptr) {
+                                                T* lw = nullptr) {
   constexpr int NB = nbasis_c(M, D);
   constexpr int NL = NB - 1;
   constexpr int NS = D + 1;
@@ -354,7 +354,8 @@ __device__ __forceinline__ void finish_variable(const KParams<T>& p, uint32_t io
     // summed in the order of the evaluation kernel (same bits); the blended
     // coefficients wait in the lane's LDS column lw[l * kHaloBlock] so that
     // they hold no registers while the other variables' sums are live, and
-    // the basis values at the points come from the LDS copy lphi
+    // the basis values at the points, the same for every lane, are read
+    // through the constant address space (scalar loads into SGPRs)
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       T x = c0 * po[l];
@@ -368,8 +369,10 @@ __device__ __forceinline__ void finish_variable(const KParams<T>& p, uint32_t io
     T w[NL];
 #pragma unroll
     for (int l = 0; l < NL; ++l) w[l] = lw[l * kHaloBlockLanes];
+    using cT = __attribute__((address_space(4))) const T;
+    const cT* const phi = (const cT*)p.phi;
     for (int q = 0; q < p.npts; ++q) {
-      const T* f = lphi + q * NB;
+      const cT* f = phi + q * NB;
       T x = fma(f[0], qi, T(0));
 #pragma unroll
       for (int l = 0; l < NL; ++l) x = fma(f[l + 1], w[l], x);
