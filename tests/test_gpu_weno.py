@@ -76,3 +76,28 @@ def test_weno_reproduces_polynomials_and_refuses_other_forms():
         lm.reconstruct(q, sigma=torch.zeros((2, 4, lm.n_cells), dtype=torch.float64, device="cuda:0"))
     with pytest.raises(C.CwenoError):
         C.Batch([lm], [2], dtype="f64")
+
+
+@pytest.mark.parametrize("name,mk,M", [("tri16_M2", lambda: tri_mesh(16, 0.15, 910), 2),
+                                       ("kuhn16_M2", lambda: kuhn_tet_mesh(16, 0.1, 911), 2)])
+def test_weno_variable_grouping_is_bitwise_invariant(name, mk, M):
+    """The variables of a call are split into passes and, within a pass, over
+    the lanes of a cell's group (up to 8 lanes, several variables each); each
+    variable's arithmetic does not depend on that split, so 25 variables in
+    one call (groups of several lanes, more than one pass) give the bits of
+    the same variables reconstructed one, five and thirteen at a time."""
+    torch = torch_cuda()
+    import paper_1612_09335_amd as C
+    m = mk()
+    print(f"[gpu weno] grouping {name}: {m.n_cells} cells", flush=True)
+    lm = C.Mesh(m.vertices, m.cells, M, periodic=m.box, weno=True)
+    rng = np.random.default_rng(912)
+    Q = rng.normal(size=(25, m.n_cells)) + 3.0 * (rng.random((1, m.n_cells)) < 0.3)
+    q = torch.tensor(Q, device="cuda:0")
+    full = lm.reconstruct(q)
+    torch.cuda.synchronize()
+    assert torch.isfinite(full).all()
+    for a, b in ((0, 1), (7, 8), (24, 25), (3, 8), (10, 23)):
+        part = lm.reconstruct(q[a:b].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(part, full[a:b]), (name, a, b)
