@@ -43,9 +43,10 @@ __global__ __launch_bounds__(kWenoBlockCells * kWenoMaxGroup) void weno_kernel(W
   // stage the block's halo, cell-fastest so that runs of consecutive cells
   // read consecutive addresses
   const int h0 = p.hoff[b], hn = p.hoff[b + 1] - h0;
-  for (int t = tid; t < hn * nvp; t += nthr) {
-    const int v = t / hn, hc = t - v * hn;
-    lq[hc * nvp + v] = p.q[(int64_t)(p.v0 + v) * nc + p.halo[h0 + hc]];
+  for (int hc = tid; hc < hn; hc += nthr) {
+    const int64_t c = p.halo[h0 + hc];
+    const double* qc = p.q + (int64_t)p.v0 * nc + c;
+    for (int v = 0; v < nvp; ++v) lq[hc * nvp + v] = qc[(int64_t)v * nc];
   }
   __syncthreads();
 
