@@ -853,7 +853,10 @@ void moving_kernel(MParams<T> p) {
         for (int s = 1; s <= NS; ++s)
           if (lam[s] > 0.0) mmin = fmin(mmin, ms[s]);
 #pragma unroll
-        for (int s = 0; s <= NS; ++s) om[s] = mmin / ms[s];   // FP64: even (m_min / eps)^r stays finite
+        // every kept ratio is at most 1, so its power cannot overflow; a
+        // dropped sector (lambda_s = 0, sigma_s = 0) gets ratio 0, since
+        // (m_min / eps)^r overflows for large r or data, and inf * 0 is NaN
+        for (int s = 0; s <= NS; ++s) om[s] = lam[s] > 0.0 ? mmin / ms[s] : 0.0;
         powi<NS + 1, double>(om, p.r);
         double tot = 0.0;
 #pragma unroll
