@@ -25,12 +25,20 @@ Parity status of each part (what pins it, from outside the oracle itself):
                   gives sigma = 0; exact-rational pipeline on tiny meshes;
                   conservation; convergence on smooth data; no overshoot at
                   jumps.
-* dropped-sector rule -- parity unpinned (the paper assumes non-degenerate
-                  stencils and gives no rule).
+* dropped-sector rule -- the emptiness decision re-derived from exact
+                  barycentric coordinates and brute-force hop distances; the
+                  1e10 condition threshold decided exactly from the
+                  characteristic polynomial of B^T B (collinear and
+                  near-collinear hand-built sectors); the exact-rational
+                  pipeline renormalising lambda on its own.
+* options      -- face sector rule on a hand-built mesh and through the exact
+                  pipeline; sigma_0 of P_opt through the exact pipeline.
 * classical WENO (weno.py, the paper's comparison scheme) -- every stencil's
                   polynomial reproduces degree-M data, so the blend does;
                   conservation; cone and reverse-cone membership re-derived by
-                  independent barycentric solves; stencil sizes.
+                  independent barycentric solves; stencil sizes; the weights
+                  (default and the paper's pair, with dropped stencils)
+                  against exact per-stencil KKT solves.
 """
 from .basis import n_basis, sigma_matrix, evaluate as evaluate_basis, index_list
 from .cweno import CwenoOracle, Options, linear_weights, stencil_size, evaluate_polynomial

@@ -38,10 +38,11 @@ class WenoOracle:
         self.d, self.M, self.nb, self.n_e = self.cw.d, self.cw.M, self.cw.nb, self.cw.n_e
         self.n_s = 1 + 2 * (self.d + 1)
         if opts.lambda0 == "paper":       # 1e5 for the central stencil, 1 per sector stencil, normalised
-            l0 = 1e5 / (1e5 + self.n_s - 1)
+            tot = 1e5 + (self.n_s - 1)
+            self.lam = np.array([1e5 / tot] + [1.0 / tot] * (self.n_s - 1))
         else:
             l0 = 0.95 if opts.lambda0 == 0.0 else float(opts.lambda0)
-        self.lam = np.array([l0] + [(1.0 - l0) / (self.n_s - 1)] * (self.n_s - 1))
+            self.lam = np.array([l0] + [(1.0 - l0) / (self.n_s - 1)] * (self.n_s - 1))
         self.opts = opts
         self._cache = {}
 

@@ -230,7 +230,7 @@ cweno_status reconstruct_weno(const cweno_mesh* m, int n_vars, cweno_dtype dtype
   p.hoff = (const int32_t*)m->whoff.p;
   p.alive = (const uint16_t*)m->walive.p;
   p.lam0 = m->lam[0];
-  p.lams = (1.0 - m->lam[0]) / (m->n_s - 1);
+  p.lams = m->lam[1];
   p.eps = m->eps;
   p.nc = m->nc;
   p.Np = m->Np;
@@ -322,16 +322,18 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
   if (!(f > 0.0)) return fail(CWENO_E_ARG, "stencil factor must be positive");
   m->n_e = (int)std::ceil(f * m->nb);
   if (m->n_e < m->nb) return fail(CWENO_E_ARG, "central stencil smaller than the basis");
-  if (o.lambda0 < 0.0) {
-    double tot = 1e5 + (dim + 1);
+  // lam[1..] is the weight of each sectorial stencil: d+1 of them for CWENO,
+  // 2(d+1) for the classical WENO scheme
+  const int n_sec = (o.flags & CWENO_FLAG_WENO) ? 2 * (dim + 1) : dim + 1;
+  if (o.lambda0 < 0.0) {   // the paper's pair: 1e5 for the central stencil, 1 per sector, normalised
+    const double tot = 1e5 + n_sec;
     m->lam[0] = 1e5 / tot;
     for (int s = 1; s <= dim + 1; ++s) m->lam[s] = 1.0 / tot;
-    if (o.flags & CWENO_FLAG_WENO) m->lam[0] = 1e5 / (1e5 + 2 * (dim + 1));   // 1e5 against 1 per sector stencil
   } else {
     double l0 = o.lambda0 == 0.0 ? 0.95 : o.lambda0;
     if (!(l0 > 0.0 && l0 < 1.0)) return fail(CWENO_E_ARG, "lambda0 must lie in (0, 1)");
     m->lam[0] = l0;
-    for (int s = 1; s <= dim + 1; ++s) m->lam[s] = (1.0 - l0) / (dim + 1);
+    for (int s = 1; s <= dim + 1; ++s) m->lam[s] = (1.0 - l0) / n_sec;
   }
   m->eps = o.eps == 0.0 ? 1e-14 : o.eps;
   if (!(m->eps > 0.0)) return fail(CWENO_E_ARG, "eps must be positive");
