@@ -388,15 +388,20 @@ cweno_status cweno_batch_group(const cweno_batch* batch, int g, int* dim, int* d
 cweno_status cweno_batch_destroy(cweno_batch* batch);
 
 /*
- * Serving: registered meshes, HBM residency under a budget, requests scheduled
- * as they arrive.
+ * Serving: registered meshes, HBM residency under a budget, requests batched
+ * as they arrive (continuous batching).
  *
  * cweno_server_create    an HBM arena of hbm_budget_bytes is allocated now (the
  *                        serving loop never allocates or frees device memory);
  *                        operators are kept in precision op_dtype; at most
- *                        max_inflight requests run at once, spread over
- *                        n_streams compute streams.  A scheduler thread and a
- *                        completion thread start here.
+ *                        max_inflight launches (1..256) run at once, spread
+ *                        over n_streams compute streams (1..16).  Each launch
+ *                        carries the requests queued when it starts, up to
+ *                        64 (cweno_server_set_batch) and what one launch
+ *                        table holds (512 variable blocks, 65,536 blocks of
+ *                        256 cells); a request too large for the table, or
+ *                        whose block halos do not fit in LDS, runs alone.
+ *                        A scheduler thread and a completion thread start here.
  * cweno_server_register  host precompute of a mesh (arguments as for
  *                        cweno_mesh_create; opt->ops and HOST_ONLY are set by
  *                        the server) and one pinned host image of its whole
@@ -414,17 +419,28 @@ cweno_status cweno_batch_destroy(cweno_batch* batch);
  *                        returns a ticket.  Requests are admitted in
  *                        submission order; a mesh that is not resident is
  *                        uploaded into the arena, evicting the least recently
- *                        used meshes that no running request uses.
+ *                        used meshes that no running request uses.  Results
+ *                        are the same bits as cweno_reconstruct's, alone or
+ *                        batched with other requests.
  * cweno_server_poll      *done = 1 once the request has finished (or was
  *                        cancelled: CWENO_E_CANCELLED; or failed: CWENO_E_HIP).
  * cweno_server_wait      blocks until the request finishes or timeout_s passes
  *                        (timeout_s < 0: no limit; CWENO_E_BUSY on timeout).
+ *                        Once poll or wait has reported a final state (done,
+ *                        cancelled, failed), the ticket is released: later
+ *                        calls with it return CWENO_E_ARG (unknown ticket).
  * cweno_server_cancel    removes a request that has not started
  *                        (CWENO_E_BUSY if it is running or finished).
  * cweno_server_stats     latency quantiles in seconds (completion seen by the
  *                        host minus submission), completed requests, evictions,
  *                        uploads and uploaded bytes since creation or the last
  *                        cweno_server_reset_stats.  Any pointer may be NULL.
+ * cweno_server_set_batch requests one launch may carry (1..512; 1 = every
+ *                        request launched on its own).
+ * cweno_server_launch_stats  launches started, requests that shared a launch
+ *                        with others, the most requests in one launch (since
+ *                        creation or the last reset), and the tickets the
+ *                        server still holds (not yet reported final).
  * cweno_server_pause     paused != 0 holds admission (submitted requests stay
  *                        queued and can be cancelled); 0 resumes it.
  * cweno_server_destroy   cancels queued requests, waits for running ones.
@@ -446,6 +462,9 @@ cweno_status cweno_server_cancel(cweno_server* server, int64_t ticket);
 cweno_status cweno_server_stats(cweno_server* server, double* p50_s, double* p99_s, double* p999_s,
                                 int64_t* completed, int64_t* evictions, int64_t* uploads, int64_t* upload_bytes);
 cweno_status cweno_server_reset_stats(cweno_server* server);
+cweno_status cweno_server_set_batch(cweno_server* server, int max_batch);
+cweno_status cweno_server_launch_stats(cweno_server* server, int64_t* launches, int64_t* shared_requests,
+                                       int64_t* largest_launch, int64_t* tickets_held);
 cweno_status cweno_server_pause(cweno_server* server, int paused);
 cweno_status cweno_server_destroy(cweno_server* server);
 

@@ -34,7 +34,8 @@ SYMBOLS = ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_
            "cweno_mesh_tune", "cweno_batch_create", "cweno_batch_run", "cweno_batch_info", "cweno_batch_group",
            "cweno_batch_destroy", "cweno_server_create", "cweno_server_register", "cweno_server_register_mesh",
            "cweno_server_mesh_info", "cweno_server_submit", "cweno_server_poll", "cweno_server_wait", "cweno_server_cancel",
-           "cweno_server_stats", "cweno_server_reset_stats", "cweno_server_pause", "cweno_server_destroy")
+           "cweno_server_stats", "cweno_server_reset_stats", "cweno_server_set_batch", "cweno_server_launch_stats",
+           "cweno_server_pause", "cweno_server_destroy")
 
 
 class CwenoError(RuntimeError):
@@ -108,6 +109,8 @@ def _load():
     dp = ctypes.POINTER(ctypes.c_double)
     lib.cweno_server_stats.argtypes = [vp, dp, dp, dp, i64p, i64p, i64p, i64p]
     lib.cweno_server_reset_stats.argtypes = [vp]
+    lib.cweno_server_set_batch.argtypes = [vp, ctypes.c_int]
+    lib.cweno_server_launch_stats.argtypes = [vp, i64p, i64p, i64p, i64p]
     lib.cweno_server_pause.argtypes = [vp, ctypes.c_int]
     lib.cweno_server_destroy.argtypes = [vp]
     for name in ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_mesh_tables",
@@ -117,7 +120,8 @@ def _load():
                  "cweno_server_create", "cweno_server_register", "cweno_server_register_mesh",
                  "cweno_server_mesh_info", "cweno_server_submit",
                  "cweno_server_poll", "cweno_server_wait", "cweno_server_cancel", "cweno_server_stats",
-                 "cweno_server_reset_stats", "cweno_server_pause", "cweno_server_destroy"):
+                 "cweno_server_reset_stats", "cweno_server_set_batch", "cweno_server_launch_stats",
+                 "cweno_server_pause", "cweno_server_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -428,15 +432,18 @@ class Batch:
 
 class Server:
     """Serving loop (cweno_server_*): registered meshes, HBM residency under a
-    budget with least-recently-used eviction, requests scheduled as they arrive."""
+    budget with least-recently-used eviction, requests batched as they arrive
+    (max_inflight launches in flight, each carrying up to max_batch requests)."""
 
-    def __init__(self, hbm_budget_bytes: int, dtype: str = "f32", max_inflight: int = 8, n_streams: int = 4):
+    def __init__(self, hbm_budget_bytes: int, dtype: str = "f32", max_inflight: int = 8, n_streams: int = 4,
+                 max_batch: int = 64):
         self.dtype = dtype
         h = ctypes.c_void_p()
         _check(lib.cweno_server_create(int(hbm_budget_bytes), {"f64": F64, "f32": F32}[dtype], int(max_inflight),
                                        int(n_streams), ctypes.byref(h)))
         self._h = h
         self._meshes = {}
+        self.set_batch(max_batch)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -509,6 +516,16 @@ class Server:
 
     def reset_stats(self):
         _check(lib.cweno_server_reset_stats(self._h))
+
+    def set_batch(self, max_batch: int):
+        """Requests one launch may carry (1: every request launched on its own)."""
+        _check(lib.cweno_server_set_batch(self._h, int(max_batch)))
+
+    def launch_stats(self):
+        la, sh, big, held = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.cweno_server_launch_stats(self._h, ctypes.byref(la), ctypes.byref(sh), ctypes.byref(big),
+                                             ctypes.byref(held)))
+        return dict(launches=la.value, shared_requests=sh.value, largest_launch=big.value, tickets_held=held.value)
 
 
 def _stream_ptr(stream):

@@ -1,6 +1,6 @@
 // Serving loop: registered meshes whose operators live in pinned host memory
 // and move in and out of HBM under a byte budget, with reconstruction
-// requests scheduled as they arrive.
+// requests batched as they arrive.
 //
 // * Registration runs the host precompute once and keeps one pinned host
 //   image of the mesh's whole device layout (operators in the server's
@@ -9,14 +9,23 @@
 //   meshes are placed first-fit (256-byte granules) and the least recently
 //   used mesh with no request in flight is evicted when a placement fails.
 //   The serving loop never allocates or frees device memory.
-// * A scheduler thread admits queued requests in arrival order, up to
-//   max_inflight at a time: it makes the mesh resident (upload on one of two
-//   copy streams, recorded in an event), pins it, and launches the reconstruction
-//   on one of several compute streams (round robin) after the upload event,
-//   so that a request waiting for its upload does not hold back the others.
-// * A completion thread polls the in-flight requests' events, records each
-//   latency (completion seen by the host minus submission), unpins meshes and
-//   wakes waiters.
+// * Continuous batching: whenever a launch may start (fewer than max_inflight
+//   launches in flight), a scheduler thread takes the queued requests in
+//   arrival order, as many as fit one launch (at most max_batch requests and
+//   one launch table), makes their meshes resident (uploads on two copy
+//   streams, each recorded in an event) and pins them.  A lone request runs
+//   as the ordinary per-mesh launch; several run as one launch of the batched
+//   persistent kernel per (dimension, degree, variable block) group over a
+//   work list of (request block, 256-cell block) items, whose kernel
+//   parameters come from a launch table (pinned host slot copied to a device
+//   slot on the launch stream).  Requests that arrive while launches are in
+//   flight queue up and leave together in the next launch.
+// * Launches go round robin over several compute streams, each behind the
+//   upload events of its meshes, so work of different launches overlaps on
+//   the device and a launch waiting for an upload holds back no other.
+// * A completion thread polls the in-flight launches' events, records each
+//   request's latency (completion seen by the host minus submission), unpins
+//   meshes, frees the launch's table slot and wakes waiters.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +43,7 @@
 
 #include "cweno.h"
 #include "mesh.hpp"
+#include "pack.hpp"
 
 using cweno_abi::fail;
 
@@ -112,16 +122,28 @@ struct Req {
   void* coeffs = nullptr;
   double t_submit = 0.0;
   int state = kQueued;
-  hipEvent_t done = nullptr;
+  int waiters = 0;                 // threads blocked in cweno_server_wait on this ticket
   double latency = 0.0;
 };
+
+// One launch: the requests it carries, its completion event and its table slot.
+struct Launch {
+  std::vector<int64_t> tickets;
+  hipEvent_t done = nullptr;
+  int slot = -1;                   // -1: a lone request launched as the per-mesh kernel
+};
+
+constexpr int kDefaultBatch = 64;       // requests one launch may carry
+constexpr int kSlotEntries = 512;       // (request, variable block) entries of one launch table
+constexpr int kSlotItems = 1 << 16;     // (entry, 256-cell block) work items of one launch table
 
 }  // namespace
 
 struct cweno_server {
   bool f32 = true;
   int device = -1;
-  int max_inflight = 8;
+  int max_inflight = 8;              // launches in flight
+  int max_batch = kDefaultBatch;     // requests per launch
   size_t budget = 0;
   void* arena_base = nullptr;
   Arena arena;
@@ -130,15 +152,21 @@ struct cweno_server {
   std::vector<hipStream_t> comp;
   int next_stream = 0;
   std::vector<std::unique_ptr<SMesh>> meshes;
-  std::unordered_map<int64_t, Req> reqs;
+  std::unordered_map<int64_t, Req> reqs;   // element addresses survive rehashing
   std::deque<int64_t> queue;
-  std::vector<int64_t> inflight;
+  std::vector<Launch> running;
   std::vector<hipEvent_t> event_pool;
+  // launch tables: one slot per launch in flight, pinned host and device copies
+  size_t param_bytes = 0, slot_bytes = 0;
+  char* h_slots = nullptr;
+  char* d_slots = nullptr;
+  std::vector<int> free_slots;
   int64_t next_ticket = 1;
   uint64_t clock = 0;
   // statistics
   std::vector<double> latencies;
   int64_t evictions = 0, uploads = 0, completed = 0, upload_bytes = 0;
+  int64_t launches = 0, shared_requests = 0, largest_launch = 0;
   std::string async_error;
   // threads
   std::mutex mu;
@@ -152,6 +180,9 @@ struct cweno_server {
   void complete_loop();
   bool make_resident(SMesh& sm);
   void point_buffers(SMesh& sm, char* base);
+  hipError_t launch_lone(const Req& r, hipStream_t s);
+  hipError_t launch_table(const std::vector<int64_t>& pack, int slot, hipStream_t s);
+  void release(int64_t ticket);
 };
 
 namespace {
@@ -211,24 +242,81 @@ bool cweno_server::make_resident(SMesh& sm) {
   return true;
 }
 
+// A lone request: the per-mesh kernel with the mesh's own variant choice.
+hipError_t cweno_server::launch_lone(const Req& r, hipStream_t s) {
+  const cweno_mesh* m = meshes[r.mesh]->m.get();
+  hipError_t e = hipSuccess;
+  for (int v0 = 0; v0 < r.n_vars && e == hipSuccess;) {
+    const int vb = cweno::pick_vb(m->d, m->M, r.n_vars - v0, f32);
+    e = cweno_abi::launch_block(m, f32, r.q, r.coeffs, nullptr, nullptr, v0, vb, m->variant[f32][vb], s);
+    v0 += vb;
+  }
+  return e;
+}
+
+// Several requests in one launch, packed into the slot's table (the batched
+// persistent kernel, one launch per (dimension, degree, block size) group).
+hipError_t cweno_server::launch_table(const std::vector<int64_t>& pack, int slot, hipStream_t s) {
+  std::vector<cweno_abi::PackRequest> rq;
+  for (int64_t t : pack) {
+    const Req& r = reqs.at(t);
+    rq.push_back({meshes[r.mesh]->m.get(), r.q, r.coeffs, r.n_vars});
+  }
+  char* h = h_slots + (size_t)slot * slot_bytes;
+  char* d = d_slots + (size_t)slot * slot_bytes;
+  const size_t items_off = (size_t)kSlotEntries * param_bytes;
+  std::vector<cweno_abi::PackGroup> groups;
+  int n_entries = 0;
+  int64_t n_items = 0;
+  cweno_abi::pack_requests(rq.data(), (int)rq.size(), f32, h, reinterpret_cast<cweno::BatchItem*>(h + items_off),
+                           groups, n_entries, n_items);
+  hipError_t e = hipMemcpyAsync(d, h, (size_t)n_entries * param_bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d + items_off, h + items_off, (size_t)n_items * sizeof(cweno::BatchItem),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = cweno_abi::launch_packed(groups, f32, d, reinterpret_cast<const cweno::BatchItem*>(d + items_off), s);
+  return e;
+}
+
 void cweno_server::schedule_loop() {
   if (hipSetDevice(device) != hipSuccess) return;
   std::unique_lock<std::mutex> lk(mu);
+  std::vector<int64_t> pack;
+  std::vector<SMesh*> used;
   while (true) {
-    cv_sched.wait(lk, [&] { return stop || (!paused && !queue.empty() && (int)inflight.size() < max_inflight); });
+    cv_sched.wait(lk, [&] { return stop || (!paused && !queue.empty() && (int)running.size() < max_inflight); });
     if (stop) break;
-    const int64_t t = queue.front();
-    Req& r = reqs[t];
-    SMesh& sm = *meshes[r.mesh];
-    if (!make_resident(sm)) {
+    // the longest prefix of the queue that fits one launch and whose meshes
+    // can be made resident now
+    pack.clear();
+    used.clear();
+    int entries = 0;
+    int64_t items = 0;
+    bool table = false;
+    for (size_t at = 0; at < queue.size() && (int)pack.size() < max_batch; ++at) {
+      const Req& r = reqs.at(queue[at]);
+      SMesh& sm = *meshes[r.mesh];
+      const cweno_abi::PackFootprint f = cweno_abi::pack_footprint(sm.m.get(), r.n_vars, f32);
+      const bool fits = f.halo_ok && entries + f.entries <= kSlotEntries && items + f.items <= kSlotItems;
+      if (!pack.empty() && !fits) break;
+      if (!make_resident(sm)) break;
+      sm.pins++;
+      sm.last_use = ++clock;
+      used.push_back(&sm);
+      pack.push_back(queue[at]);
+      entries += f.entries;
+      items += f.items;
+      if (!fits) break;             // runs alone as the per-mesh kernel
+      table = pack.size() > 1;
+    }
+    if (pack.empty()) {
       // every other resident mesh is in use: a completion will free one
       cv_sched.wait_for(lk, std::chrono::milliseconds(1));
       continue;
     }
-    queue.pop_front();
-    sm.pins++;
-    sm.last_use = ++clock;
-    r.state = kRunning;
+    queue.erase(queue.begin(), queue.begin() + (std::ptrdiff_t)pack.size());
+    for (int64_t t : pack) reqs.at(t).state = kRunning;
     hipStream_t s = comp[next_stream];
     next_stream = (next_stream + 1) % (int)comp.size();
     if (event_pool.empty()) {
@@ -236,49 +324,64 @@ void cweno_server::schedule_loop() {
       if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
       event_pool.push_back(ev);
     }
-    r.done = event_pool.back();
+    Launch L;
+    L.tickets = pack;
+    L.done = event_pool.back();
     event_pool.pop_back();
-    hipError_t e = r.done ? hipStreamWaitEvent(s, sm.ready, 0) : hipErrorInvalidValue;
-    const cweno_mesh* m = sm.m.get();
-    for (int v0 = 0; v0 < r.n_vars && e == hipSuccess;) {
-      const int vb = cweno::pick_vb(m->d, m->M, r.n_vars - v0, f32);
-      e = cweno_abi::launch_block(m, f32, r.q, r.coeffs, nullptr, nullptr, v0, vb, m->variant[f32][vb], s);
-      v0 += vb;
+    hipError_t e = L.done ? hipSuccess : hipErrorInvalidValue;
+    std::sort(used.begin(), used.end());
+    used.erase(std::unique(used.begin(), used.end()), used.end());
+    for (SMesh* sm : used)
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, sm->ready, 0);
+    if (e == hipSuccess) {
+      if (table) {
+        L.slot = free_slots.back();   // one slot per launch in flight: never empty here
+        free_slots.pop_back();
+        e = launch_table(pack, L.slot, s);
+      } else {
+        e = launch_lone(reqs.at(pack[0]), s);
+      }
     }
-    if (e == hipSuccess) e = hipEventRecord(r.done, s);
+    if (e == hipSuccess) e = hipEventRecord(L.done, s);
     if (e != hipSuccess) {
-      r.state = kFailed;
+      // the launch did not start as a whole: its requests fail (work that did
+      // start finishes before the stream is used again)
       async_error = std::string("launch failed: ") + hipGetErrorString(e);
-      sm.pins--;
-      if (r.done) event_pool.push_back(r.done);
-      r.done = nullptr;
+      (void)hipStreamSynchronize(s);
+      for (int64_t t : pack) {
+        reqs.at(t).state = kFailed;
+        meshes[reqs.at(t).mesh]->pins--;
+      }
+      if (L.slot >= 0) free_slots.push_back(L.slot);
+      if (L.done) event_pool.push_back(L.done);
       cv_done.notify_all();
       continue;
     }
-    inflight.push_back(t);
+    ++launches;
+    if (pack.size() > 1) shared_requests += (int64_t)pack.size();
+    largest_launch = std::max(largest_launch, (int64_t)pack.size());
+    running.push_back(std::move(L));
     cv_inflight.notify_all();
   }
 }
 
 void cweno_server::complete_loop() {
   if (hipSetDevice(device) != hipSuccess) return;
-  std::vector<int64_t> snapshot, finished;
+  std::vector<hipEvent_t> snapshot;
+  std::vector<size_t> finished;
   while (true) {
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv_inflight.wait(lk, [&] { return !inflight.empty() || (stop && inflight.empty()); });
-      if (inflight.empty() && stop) break;
-      snapshot = inflight;
+      cv_inflight.wait(lk, [&] { return !running.empty() || stop; });
+      if (running.empty() && stop) break;
+      snapshot.clear();
+      for (const Launch& L : running) snapshot.push_back(L.done);
     }
+    // only this thread removes launches, so the first snapshot.size() entries
+    // of `running` are still the ones polled here
     finished.clear();
-    for (int64_t t : snapshot) {
-      hipEvent_t ev;
-      {
-        std::lock_guard<std::mutex> g(mu);
-        ev = reqs[t].done;
-      }
-      if (hipEventQuery(ev) != hipErrorNotReady) finished.push_back(t);
-    }
+    for (size_t k = 0; k < snapshot.size(); ++k)
+      if (hipEventQuery(snapshot[k]) != hipErrorNotReady) finished.push_back(k);
     if (finished.empty()) {
       std::this_thread::yield();
       continue;
@@ -286,25 +389,34 @@ void cweno_server::complete_loop() {
     const double t_done = now_s();
     {
       std::lock_guard<std::mutex> g(mu);
-      for (int64_t t : finished) {
-        Req& r = reqs[t];
-        const hipError_t e = hipEventQuery(r.done);
-        r.state = e == hipSuccess ? kDone : kFailed;
+      for (auto it = finished.rbegin(); it != finished.rend(); ++it) {
+        Launch& L = running[*it];
+        const hipError_t e = hipEventQuery(L.done);
         if (e != hipSuccess) async_error = std::string("request failed: ") + hipGetErrorString(e);
-        r.latency = t_done - r.t_submit;
-        if (r.state == kDone) {
-          latencies.push_back(r.latency);
-          ++completed;
+        for (int64_t t : L.tickets) {
+          Req& r = reqs.at(t);
+          r.state = e == hipSuccess ? kDone : kFailed;
+          r.latency = t_done - r.t_submit;
+          if (r.state == kDone) {
+            latencies.push_back(r.latency);
+            ++completed;
+          }
+          meshes[r.mesh]->pins--;
         }
-        meshes[r.mesh]->pins--;
-        event_pool.push_back(r.done);
-        r.done = nullptr;
-        inflight.erase(std::find(inflight.begin(), inflight.end(), t));
+        event_pool.push_back(L.done);
+        if (L.slot >= 0) free_slots.push_back(L.slot);
+        running.erase(running.begin() + (std::ptrdiff_t)*it);
       }
     }
     cv_sched.notify_all();
     cv_done.notify_all();
   }
+}
+
+// Forget a request whose final state has been reported (caller holds mu).
+void cweno_server::release(int64_t ticket) {
+  auto it = reqs.find(ticket);
+  if (it != reqs.end() && it->second.state >= kDone && it->second.waiters == 0) reqs.erase(it);
 }
 
 cweno_server::~cweno_server() {
@@ -336,6 +448,8 @@ cweno_server::~cweno_server() {
     if (sm->image) (void)hipHostFree(sm->image);
   }
   if (arena_base) (void)hipFree(arena_base);
+  if (d_slots) (void)hipFree(d_slots);
+  if (h_slots) (void)hipHostFree(h_slots);
 }
 
 namespace {
@@ -399,7 +513,7 @@ cweno_status cweno_server_create(int64_t hbm_budget_bytes, cweno_dtype op_dtype,
   *out = nullptr;
   if (hbm_budget_bytes <= 0) return fail(CWENO_E_ARG, "budget must be positive");
   if (op_dtype != CWENO_F32 && op_dtype != CWENO_F64) return fail(CWENO_E_ARG, "bad dtype");
-  if (max_inflight < 1 || max_inflight > 1024) return fail(CWENO_E_ARG, "max_inflight must be in 1..1024");
+  if (max_inflight < 1 || max_inflight > 256) return fail(CWENO_E_ARG, "max_inflight must be in 1..256");
   if (n_streams < 1 || n_streams > 16) return fail(CWENO_E_ARG, "n_streams must be in 1..16");
   std::unique_ptr<cweno_server> s(new (std::nothrow) cweno_server());
   if (!s) return fail(CWENO_E_NOMEM, "host allocation failed");
@@ -411,6 +525,13 @@ cweno_status cweno_server_create(int64_t hbm_budget_bytes, cweno_dtype op_dtype,
   if (hipMalloc(&s->arena_base, s->budget) != hipSuccess)
     return fail(CWENO_E_NOMEM, "cannot allocate an HBM arena of the requested budget");
   s->arena.reset(s->budget);
+  // launch tables: one slot per launch in flight
+  s->param_bytes = s->f32 ? sizeof(cweno::KParams<float>) : sizeof(cweno::KParams<double>);
+  s->slot_bytes = round_up((size_t)kSlotEntries * s->param_bytes + (size_t)kSlotItems * sizeof(cweno::BatchItem));
+  if (hipMalloc(&s->d_slots, s->slot_bytes * (size_t)max_inflight) != hipSuccess ||
+      hipHostMalloc(&s->h_slots, s->slot_bytes * (size_t)max_inflight, hipHostMallocDefault) != hipSuccess)
+    return fail(CWENO_E_NOMEM, "cannot allocate the launch tables");
+  for (int k = max_inflight - 1; k >= 0; --k) s->free_slots.push_back(k);
   s->copy.assign(kCopyStreams, nullptr);
   for (hipStream_t& x : s->copy)
     if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess)
@@ -545,9 +666,11 @@ cweno_status cweno_server_poll(cweno_server* s, int64_t ticket, int* done) {
   std::lock_guard<std::mutex> g(s->mu);
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return fail(CWENO_E_ARG, "unknown ticket");
-  *done = it->second.state >= kDone ? 1 : 0;
-  if (it->second.state == kCancelled) return fail(CWENO_E_CANCELLED, "request was cancelled");
-  if (it->second.state == kFailed) return fail(CWENO_E_HIP, "request failed: " + s->async_error);
+  const int state = it->second.state;
+  *done = state >= kDone ? 1 : 0;
+  s->release(ticket);                // a reported final state ends the ticket
+  if (state == kCancelled) return fail(CWENO_E_CANCELLED, "request was cancelled");
+  if (state == kFailed) return fail(CWENO_E_HIP, "request failed: " + s->async_error);
   return CWENO_OK;
 }
 
@@ -556,12 +679,20 @@ cweno_status cweno_server_wait(cweno_server* s, int64_t ticket, double timeout_s
   std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return fail(CWENO_E_ARG, "unknown ticket");
-  const auto pred = [&] { return it->second.state >= kDone; };
+  // the element itself (not the iterator) stays valid while the map grows;
+  // it is erased only once no thread waits on it
+  Req* r = &it->second;
+  r->waiters++;
+  const auto pred = [&] { return r->state >= kDone; };
+  bool finished = true;
   if (timeout_s < 0) s->cv_done.wait(lk, pred);
-  else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred))
-    return fail(CWENO_E_BUSY, "timed out");
-  if (it->second.state == kCancelled) return fail(CWENO_E_CANCELLED, "request was cancelled");
-  if (it->second.state == kFailed) return fail(CWENO_E_HIP, "request failed: " + s->async_error);
+  else finished = s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred);
+  r->waiters--;
+  const int state = r->state;
+  if (!finished) return fail(CWENO_E_BUSY, "timed out");
+  s->release(ticket);
+  if (state == kCancelled) return fail(CWENO_E_CANCELLED, "request was cancelled");
+  if (state == kFailed) return fail(CWENO_E_HIP, "request failed: " + s->async_error);
   return CWENO_OK;
 }
 
@@ -574,6 +705,25 @@ cweno_status cweno_server_cancel(cweno_server* s, int64_t ticket) {
   s->queue.erase(std::find(s->queue.begin(), s->queue.end(), ticket));
   it->second.state = kCancelled;
   s->cv_done.notify_all();
+  return CWENO_OK;
+}
+
+cweno_status cweno_server_set_batch(cweno_server* s, int max_batch) {
+  if (!s) return fail(CWENO_E_ARG, "server is NULL");
+  if (max_batch < 1 || max_batch > kSlotEntries) return fail(CWENO_E_ARG, "max_batch must be in 1..512");
+  std::lock_guard<std::mutex> g(s->mu);
+  s->max_batch = max_batch;
+  return CWENO_OK;
+}
+
+cweno_status cweno_server_launch_stats(cweno_server* s, int64_t* launches, int64_t* shared_requests,
+                                       int64_t* largest_launch, int64_t* tickets_held) {
+  if (!s) return fail(CWENO_E_ARG, "server is NULL");
+  std::lock_guard<std::mutex> g(s->mu);
+  if (launches) *launches = s->launches;
+  if (shared_requests) *shared_requests = s->shared_requests;
+  if (largest_launch) *largest_launch = s->largest_launch;
+  if (tickets_held) *tickets_held = (int64_t)s->reqs.size();
   return CWENO_OK;
 }
 
@@ -606,6 +756,7 @@ cweno_status cweno_server_reset_stats(cweno_server* s) {
   std::lock_guard<std::mutex> g(s->mu);
   s->latencies.clear();
   s->completed = s->evictions = s->uploads = s->upload_bytes = 0;
+  s->launches = s->shared_requests = s->largest_launch = 0;
   return CWENO_OK;
 }
 
