@@ -22,13 +22,17 @@ must still be finite and sum to one.
 Full sizes.  The benchmark's 2-D workload (524,288 triangles, M=3, 9
 variables) and the 3-D one (1,572,864 tetrahedra, M=3, 5 variables) run in
 the benchmark's launch configuration (variant chosen by the tuner) in both
-precisions; sampled cells are compared with the oracle one by one (FP64 to
-1e-12, FP32 to the bar above) and every cell is checked for properties that
-hold at any size (bitwise coefficient 0, finite values, weights summing to 1).
+precisions.  Every cell of the 2-D workload, and 8,192 sampled cells of the
+3-D one (random ones, the first and last blocks and block edges), are
+compared with the oracle (run in a pool over the host's cores) one by one:
+FP64 to 1e-12, FP32 to the bar above.  Every cell is also checked for
+properties that hold at any size (bitwise coefficient 0, finite values,
+weights summing to 1).
 """
 import numpy as np
 import pytest
 
+import oracle_pool
 from gpu_common import data_scaled_error, run_library, torch_cuda
 from oracle import CwenoOracle, Options
 from synthetic import kuhn_tet_mesh, tri_mesh, workload_fields
@@ -94,14 +98,19 @@ def test_fp32_against_fp64_oracle(case, linear):
 
 
 def _full_size(torch, C, m, Q, M, n_sample, seed):
+    """n_sample None: every cell against the oracle."""
     lm = C.Mesh(m.vertices, m.cells, M, periodic=m.box, ops="both")
-    rng = np.random.default_rng(seed)
-    # sampled cells: random ones, the first and last blocks, and block edges
-    idx = np.unique(np.concatenate([rng.choice(m.n_cells, n_sample, replace=False), np.arange(0, 64),
-                                    np.arange(m.n_cells - 64, m.n_cells),
-                                    np.arange(255, m.n_cells, 256 * 997)]))
-    o = CwenoOracle(m.vertices, m.cells, m.box, Options(degree=M))
-    ref = o.reconstruct(Q, cells=idx)
+    if n_sample is None:
+        idx = np.arange(m.n_cells)
+    else:
+        rng = np.random.default_rng(seed)
+        # sampled cells: random ones, the first and last blocks, and block edges
+        idx = np.unique(np.concatenate([rng.choice(m.n_cells, n_sample, replace=False), np.arange(0, 64),
+                                        np.arange(m.n_cells - 64, m.n_cells),
+                                        np.arange(255, m.n_cells, 256 * 997)]))
+    print(f"[gpu full] {m.name}: oracle on {len(idx)} cells over {oracle_pool.workers()} processes", flush=True)
+    co, om = oracle_pool.reconstruct(m, Options(degree=M), Q, idx)
+    ref = {"coeffs": co, "omega": om}
     st = lm.tables()["stencil"][idx]
     for tag, tdt, np_dt in (("f64", torch.float64, np.float64), ("f32", torch.float32, np.float32)):
         q = torch.tensor(Q, dtype=tdt, device="cuda:0")
@@ -112,12 +121,12 @@ def _full_size(torch, C, m, Q, M, n_sample, seed):
         _check_properties(res, Q, np_dt)
         if tag == "f64":
             err = data_scaled_error(res["coeffs"][:, :, idx], ref["coeffs"], Q, st)
-            print(f"[gpu full]   FP64 sampled error {err:.3e} over {len(idx)} cells", flush=True)
+            print(f"[gpu full]   FP64 error {err:.3e} over {len(idx)} cells", flush=True)
             assert err <= TOL64
             assert np.abs(res["omega"][:, :, idx] - ref["omega"]).max() <= 1e-9
         else:
             emax, e999 = _errors32(res["coeffs"][:, :, idx], ref["coeffs"], Q, st)
-            print(f"[gpu full]   FP32 sampled error max {emax:.3e} p99.9 {e999:.3e}", flush=True)
+            print(f"[gpu full]   FP32 error max {emax:.3e} p99.9 {e999:.3e} over {len(idx)} cells", flush=True)
             assert emax <= TOL32 and e999 <= TOL32_P999
         del q, out, res
 
@@ -127,7 +136,7 @@ def test_full_size_tri512_M3_nv9():
     C = _lib()
     m = tri_mesh(512, 0.15, 16120935)
     Q = workload_fields(m, "mhd2d", 16120935)
-    _full_size(torch, C, m, Q, 3, 400, 1)
+    _full_size(torch, C, m, Q, 3, None, 1)
 
 
 def test_full_size_kuhn64_M3_nv5():
@@ -135,4 +144,4 @@ def test_full_size_kuhn64_M3_nv5():
     C = _lib()
     m = kuhn_tet_mesh(64, 0.1, 16120936)
     Q = workload_fields(m, "euler3d_blast", 16120936)
-    _full_size(torch, C, m, Q, 3, 120, 2)
+    _full_size(torch, C, m, Q, 3, 8192, 2)
