@@ -94,7 +94,7 @@ cweno_status alloc_zero(DevBuf& b, size_t bytes, hipStream_t s, int64_t& total) 
 cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int32_t* cells, int ops, hipStream_t s) {
   const int dim = m->d;
   int seg = 0, rpl = 0;
-  if (!cweno::move_shape(dim, m->M, m->n_e - 1, seg, rpl) || rpl != 1)
+  if (!cweno::move_shape(dim, m->M, m->n_e - 1, seg, rpl, true))
     return fail(CWENO_E_ARG, "device operator assembly supports central stencils of at most 65 cells");
   std::vector<double> lam, w, rule;
   cweno::grundmann_moller(dim, m->M, lam, w);

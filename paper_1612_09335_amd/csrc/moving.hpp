@@ -8,20 +8,25 @@
 
 namespace cweno {
 
-// Segment shapes (lanes per cell, rows per lane) instantiated for (D, M): a
-// segment of 32 lanes when the basis leaves room for the rows, 64 lanes
-// always, and 64 lanes with two rows each for the wide 3-D stencils.
+// Segment shapes (lanes per cell, rows per lane) instantiated for (D, M): the
+// rows of R must lie in the first row slot (fewer basis functions than
+// lanes), and two rows per lane on 64 lanes serve the wide 3-D stencils.
 __host__ __device__ constexpr bool move_shape_ok(int D, int M, int seg, int rpl) {
-  return (seg == 32 && rpl == 1 && nbasis_c(M, D) - 1 < 32) || (seg == 64 && rpl == 1) ||
-         (seg == 64 && rpl == 2 && D == 3 && M >= 2);
+  return (seg == 16 || seg == 32 || seg == 64) && (rpl == 1 || rpl == 2) && nbasis_c(M, D) - 1 < seg &&
+         (seg < 64 || rpl == 1 || (D == 3 && M >= 2));
 }
 
-// Smallest instantiated shape whose rows hold the NE1 stencil cells besides
-// the cell; false if none does.
-inline bool move_shape(int D, int M, int NE1, int& seg, int& rpl) {
-  const int cand[3][2] = {{32, 1}, {64, 1}, {64, 2}};
-  for (const auto& c : cand)
-    if (move_shape_ok(D, M, c[0], c[1]) && NE1 <= c[0] * c[1]) {
+// Preferred shapes, in order: the narrowest segment whose rows hold the
+// stencil, with as few rows per lane as that allows (fewer exchange stages per
+// sum, more cells per wave instruction).
+constexpr int kMoveShapes[6][2] = {{16, 1}, {16, 2}, {32, 1}, {32, 2}, {64, 1}, {64, 2}};
+
+// First instantiated shape whose rows hold the NE1 stencil cells besides the
+// cell (with one_row, among the shapes of one row per lane); false if none
+// does.
+inline bool move_shape(int D, int M, int NE1, int& seg, int& rpl, bool one_row = false) {
+  for (const auto& c : kMoveShapes)
+    if (move_shape_ok(D, M, c[0], c[1]) && NE1 <= c[0] * c[1] && (!one_row || c[1] == 1)) {
       seg = c[0];
       rpl = c[1];
       return true;

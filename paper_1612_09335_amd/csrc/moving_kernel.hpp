@@ -5,9 +5,9 @@
 // at every step (Sec. 2.1), so storing them buys nothing; this trades the
 // operator stream for arithmetic.
 //
-// Work mapping.  A segment of SEG lanes (32 or 64) owns one cell.  Lane t of
-// the segment owns rows t, t + SEG, ... (RPL rows) of the cell's least-squares
-// matrix A' (row k: stencil cell k+1).  Per cell:
+// Work mapping.  A segment of SEG lanes (16, 32 or 64) owns one cell.  Lane t
+// of the segment owns rows t, t + SEG, ... (RPL rows) of the cell's least-
+// squares matrix A' (row k: stencil cell k+1).  Per cell:
 //   1. every lane unwraps the cell's vertices (minimum image around vertex 0)
 //      and inverts its reference map x = X0 + J xi;
 //   2. each row lane places its stencil cell in that frame (translated by the
@@ -17,7 +17,9 @@
 //   3. columns are scaled to unit 2-norm and reduced by Householder
 //      reflections; the sums over the segment are butterflies (DPP within
 //      rows of 16 lanes, a swizzle across rows, lane reads across the halves
-//      of the wave).  Each reflector stays in the entries it eliminated;
+//      of the wave), so a narrower segment with more rows per lane needs
+//      fewer exchange stages per sum and serves more cells per wave
+//      instruction.  Each reflector stays in the entries it eliminated;
 //   4. one lane per sector evaluates the linear basis functions at the sector
 //      cells' barycentres (the averages of a linear function), inverts the
 //      d x d system (eq. CWENO:Ps) and drops the sector if its 2-norm
@@ -59,7 +61,7 @@ constexpr int kMoveThreads = 256;  // four waves per block
 // the 3-D degree-4 ones need all 256 and would spill heavily; the others fit
 // three or four waves unbounded.
 __host__ __device__ constexpr int move_min_waves(int D, int M, int RPL) {
-  return D == 3 && M == 3 && RPL == 1 ? 3 : 1;
+  return D == 3 && M == 3 ? (RPL == 1 ? 3 : 2) : 1;
 }
 
 template <typename T>
@@ -146,7 +148,7 @@ constexpr int kSwzXor16 = 0x401F;     // and 0x1f, xor 0x10
 // of the wave must be active.
 template <int SEG, int N>
 __device__ __forceinline__ void seg_sum(double (&x)[N], int first = 0, int last = N) {
-  static_assert(SEG == 32 || SEG == 64, "segment of 32 or 64 lanes");
+  static_assert(SEG == 16 || SEG == 32 || SEG == 64, "segment of 16, 32 or 64 lanes");
 #pragma unroll
   for (int c = 0; c < N; ++c)
     if (c >= first && c < last) x[c] += dpp_d<kDppXor1>(x[c]);
@@ -159,9 +161,11 @@ __device__ __forceinline__ void seg_sum(double (&x)[N], int first = 0, int last 
 #pragma unroll
   for (int c = 0; c < N; ++c)
     if (c >= first && c < last) x[c] += dpp_d<kDppMirror>(x[c]);
+  if constexpr (SEG >= 32) {
 #pragma unroll
-  for (int c = 0; c < N; ++c)
-    if (c >= first && c < last) x[c] += swz_d<kSwzXor16>(x[c]);
+    for (int c = 0; c < N; ++c)
+      if (c >= first && c < last) x[c] += swz_d<kSwzXor16>(x[c]);
+  }
   if constexpr (SEG == 64) {
 #pragma unroll
     for (int c = 0; c < N; ++c)
@@ -169,13 +173,17 @@ __device__ __forceinline__ void seg_sum(double (&x)[N], int first = 0, int last 
   }
 }
 
-// Value of x in lane `src` of this lane's segment (src uniform).
-template <int SEG>
-__device__ __forceinline__ double seg_bcast(double x, int src, int seg) {
-  if constexpr (SEG == 64) {
-    return rdl_d(x, src);
+// Value of x in lane SRC of this lane's segment.  A 16-lane segment is one
+// DPP row: the row's lane SRC is broadcast to the row (row_newbcast).
+template <int SEG, int SRC>
+__device__ __forceinline__ double seg_bcast(double x, int seg) {
+  static_assert(SRC >= 0 && SRC < SEG, "lane of the segment");
+  if constexpr (SEG == 16) {
+    return dpp_d<0x150 + SRC>(x);
+  } else if constexpr (SEG == 64) {
+    return rdl_d(x, SRC);
   } else {
-    const double a = rdl_d(x, src), b = rdl_d(x, src + 32);
+    const double a = rdl_d(x, SRC), b = rdl_d(x, SRC + 32);
     return seg ? b : a;
   }
 }
@@ -532,7 +540,7 @@ void moving_kernel(MParams<T> p) {
     }
     seg_sum<SEG, 1>(nn, 0);
     const double nrm = sqrt(nn[0]);
-    const double akk = seg_bcast<SEG>(A[k / SEG][k], k % SEG, seg);
+    const double akk = seg_bcast<SEG, k % SEG>(A[k / SEG][k], seg);
     const double alpha = akk > 0.0 ? -nrm : nrm;
     const double vn2 = 2.0 * nrm * (nrm + fabs(akk));   // |x - alpha e_k|^2
     if (!(vn2 > 0.0)) fault |= 2;
@@ -775,7 +783,7 @@ void moving_kernel(MParams<T> p) {
       const double ik = 1.0 / L[ORD + k];
       double xk[VB];
 #pragma unroll
-      for (int v = 0; v < VB; ++v) xk[v] = seg_bcast<SEG>(dq[0][v], k, seg) * ik;
+      for (int v = 0; v < VB; ++v) xk[v] = seg_bcast<SEG, k>(dq[0][v], seg) * ik;
       if (row[0] < k) {
         const double rk = A[0][k];
 #pragma unroll
