@@ -388,6 +388,32 @@ cweno_status cweno_batch_group(const cweno_batch* batch, int g, int* dim, int* d
 cweno_status cweno_batch_destroy(cweno_batch* batch);
 
 /*
+ * Batched reconstruction that allocates nothing, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the reconstructions of cweno_batch_create
+ * plus cweno_batch_run in one call, without a batch object, a tuner or a graph.
+ *
+ * n meshes (device meshes holding operators of `dtype`, on the current
+ * device); mesh i is reconstructed from q[i] ([n_vars[i]][n_cells_i]) into
+ * coeffs[i] ([n_vars[i]][n_basis_i][n_cells_i]), device buffers as for
+ * cweno_reconstruct, with the same bits.  The meshes' variable blocks are
+ * grouped by (dimension, degree, block size) and each group runs as one launch
+ * of the batched LDS-halo kernel.  Its launch table and work list live in a
+ * static device array of 512 KiB + 256 table entries that each GPU holds for
+ * the life of the process (filled from a static host stage with host-to-device
+ * copies on hip_stream); the call makes no hipMalloc, hipFree or other
+ * allocating call.  Limits: at most 256 variable blocks (a block holds up to 9,
+ * 5 or fewer variables depending on the basis) and 65,536 blocks of 256 cells
+ * over all meshes, else CWENO_E_ARG and nothing runs.  Every mesh's block
+ * halos must fit in LDS (CWENO_E_ARG otherwise).  Asynchronous on hip_stream;
+ * it may wait for the host-to-device copy of the previous call.  All calls on
+ * one GPU share the device array: calls on different streams that are not
+ * ordered with each other race and must not overlap.
+ */
+cweno_status cweno_batch_run_noalloc(int n, const cweno_mesh* const* meshes, const int* n_vars, cweno_dtype dtype,
+                                     const void* const* q, void* const* coeffs, void* hip_stream);
+
+/*
  * Serving: registered meshes, HBM residency under a budget, requests batched
  * as they arrive (continuous batching).
  *

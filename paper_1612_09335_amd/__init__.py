@@ -32,7 +32,7 @@ SYMBOLS = ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_
            "cweno_last_error",
            "cweno_abi_version", "cweno_num_variants", "cweno_mesh_set_variant", "cweno_mesh_get_variant",
            "cweno_mesh_tune", "cweno_batch_create", "cweno_batch_run", "cweno_batch_info", "cweno_batch_group",
-           "cweno_batch_destroy", "cweno_server_create", "cweno_server_register", "cweno_server_register_mesh",
+           "cweno_batch_destroy", "cweno_batch_run_noalloc", "cweno_server_create", "cweno_server_register", "cweno_server_register_mesh",
            "cweno_server_mesh_info", "cweno_server_submit", "cweno_server_poll", "cweno_server_wait", "cweno_server_cancel",
            "cweno_server_stats", "cweno_server_reset_stats", "cweno_server_set_batch", "cweno_server_launch_stats",
            "cweno_server_pause", "cweno_server_destroy")
@@ -95,6 +95,8 @@ def _load():
     lib.cweno_batch_group.argtypes = [vp, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 7 + [
         ctypes.POINTER(ctypes.c_double)]
     lib.cweno_batch_destroy.argtypes = [vp]
+    lib.cweno_batch_run_noalloc.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int),
+                                            ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     i64p = ctypes.POINTER(i64)
     lib.cweno_server_create.argtypes = [i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
     lib.cweno_server_register.argtypes = [vp, ctypes.c_int, i64, vp, i64, vp, ctypes.c_int, ctypes.POINTER(_Options),
@@ -117,6 +119,7 @@ def _load():
                  "cweno_mesh_operators", "cweno_mesh_weno_tables", "cweno_reconstruct", "cweno_mesh_set_variant",
                  "cweno_mesh_get_variant", "cweno_mesh_tune", "cweno_num_variants", "cweno_batch_create",
                  "cweno_batch_run", "cweno_batch_info", "cweno_batch_group", "cweno_batch_destroy",
+                 "cweno_batch_run_noalloc",
                  "cweno_server_create", "cweno_server_register", "cweno_server_register_mesh",
                  "cweno_server_mesh_info", "cweno_server_submit",
                  "cweno_server_poll", "cweno_server_wait", "cweno_server_cancel", "cweno_server_stats",
@@ -528,6 +531,29 @@ class Server:
         return dict(launches=la.value, shared_requests=sh.value, largest_launch=big.value, tickets_held=held.value)
 
 
+def batch_run_noalloc(meshes, qs, outs, dtype: str = "f64", stream=None):
+    """cweno_batch_run_noalloc: the meshes' reconstructions as batched launches
+    whose tables live in a static device array (no allocation).
+    q_i [n_vars_i, n_cells_i] -> outs_i [n_vars_i, n_basis_i, n_cells_i] (torch CUDA tensors)."""
+    import torch
+    tdt = {"f64": torch.float64, "f32": torch.float32}[dtype]
+    n = len(meshes)
+    if len(qs) != n or len(outs) != n:
+        raise ValueError("one q and one out tensor per mesh")
+    for m, q, o in zip(meshes, qs, outs):
+        if (q.dtype != tdt or not q.is_cuda or not q.is_contiguous() or q.dim() != 2 or q.shape[1] != m.n_cells
+                or o.dtype != tdt or not o.is_contiguous() or tuple(o.shape) != (q.shape[0], m.n_basis, m.n_cells)):
+            raise ValueError("q/out tensors must match each mesh's shape and the precision")
+    if stream is None:
+        stream = torch.cuda.current_stream(qs[0].device)
+    ma = (ctypes.c_void_p * n)(*[m._h.value for m in meshes])
+    nv = (ctypes.c_int * n)(*[q.shape[0] for q in qs])
+    qa = (ctypes.c_void_p * n)(*[q.data_ptr() for q in qs])
+    oa = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    _check(lib.cweno_batch_run_noalloc(n, ma, nv, {"f64": F64, "f32": F32}[dtype], qa, oa, _stream_ptr(stream)))
+    return outs
+
+
 def _stream_ptr(stream):
     if stream is None:
         return None
@@ -536,4 +562,4 @@ def _stream_ptr(stream):
     return getattr(stream, "cuda_stream", None)
 
 
-__all__ = ["Mesh", "Points", "CwenoError", "n_basis", "lib", "LIB_PATH", "SYMBOLS"]
+__all__ = ["Mesh", "Points", "CwenoError", "n_basis", "batch_run_noalloc", "lib", "LIB_PATH", "SYMBOLS"]

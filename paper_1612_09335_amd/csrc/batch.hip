@@ -15,12 +15,14 @@
 #include <cstring>
 #include <fstream>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
 
 #include "cweno.h"
 #include "mesh.hpp"
+#include "pack.hpp"
 
 using cweno_abi::fail;
 
@@ -417,3 +419,113 @@ cweno_status cweno_batch_destroy(cweno_batch* b) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched reconstruction without allocation (cweno_batch_run_noalloc).
+//
+// The launch table and work list live in `scratch`, a static device array of
+// kNoAllocBytes that each GPU holds for the life of the process.  Host code
+// never uses the array's name as an address: on a device's first call its
+// address on that device is looked up once with hipGetSymbolAddress and kept
+// per device.  The table is packed into a static host stage and copied into
+// the device array on the caller's stream; an event recorded after the copy
+// guards the host stage against the next call.  Every call on one GPU uses
+// the same device array: calls that overlap on one GPU (different streams,
+// not ordered) race.
+
+namespace {
+
+constexpr int kNoAllocEntries = 256;       // (mesh, variable block) entries
+constexpr int kNoAllocItems = 1 << 16;     // 256-cell blocks over all meshes
+constexpr size_t kNoAllocTable = (size_t)kNoAllocEntries * sizeof(cweno::KParams<double>);
+constexpr size_t kNoAllocBytes = kNoAllocTable + (size_t)kNoAllocItems * sizeof(cweno::BatchItem);
+static_assert(sizeof(cweno::KParams<float>) <= sizeof(cweno::KParams<double>), "table slot size");
+static_assert(kNoAllocTable % 256 == 0, "work list alignment");
+
+constexpr int kMaxDevices = 64;
+
+struct NoAllocDevice {
+  char* scratch = nullptr;        // the array's address on this device
+  hipEvent_t staged = nullptr;    // the last call's copy out of the host stage has finished
+};
+
+std::mutex g_noalloc_mu;
+NoAllocDevice g_noalloc[kMaxDevices];
+alignas(256) char g_noalloc_stage[kNoAllocBytes];
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+extern "C" cweno_status cweno_batch_run_noalloc(int n, const cweno_mesh* const* meshes, const int* n_vars,
+                                                cweno_dtype dtype, const void* const* q, void* const* coeffs,
+                                                void* hip_stream) {
+  if (n < 1 || !meshes || !n_vars || !q || !coeffs) return fail(CWENO_E_ARG, "need at least one mesh and its buffers");
+  if (dtype != CWENO_F64 && dtype != CWENO_F32) return fail(CWENO_E_ARG, "bad dtype");
+  const bool f32 = dtype == CWENO_F32;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return fail(CWENO_E_HIP, "no HIP device");
+  if (dev >= kMaxDevices) return fail(CWENO_E_ARG, "device index beyond the supported 64");
+  const size_t es = f32 ? 4 : 8;
+  std::vector<cweno_abi::PackRequest> rq;
+  int entries = 0;
+  int64_t items = 0;
+  for (int i = 0; i < n; ++i) {
+    const cweno_mesh* m = meshes[i];
+    const std::string who = "mesh " + std::to_string(i);
+    if (!m) return fail(CWENO_E_ARG, who + " is NULL");
+    if (m->flags & CWENO_FLAG_HOST_ONLY) return fail(CWENO_E_ARG, who + " is host-only");
+    if (m->device != dev) return fail(CWENO_E_ARG, who + " lives on another device");
+    if ((f32 && !m->pinv32.p) || (!f32 && !m->pinv64.p))
+      return fail(CWENO_E_ARG, who + " holds no operators of this precision");
+    if (n_vars[i] < 1) return fail(CWENO_E_ARG, "n_vars must be >= 1");
+    if (!q[i] || !coeffs[i]) return fail(CWENO_E_ARG, who + ": NULL buffer");
+    if ((uint64_t)m->nc * (uint64_t)m->nb * es >= (uint64_t(1) << 32))
+      return fail(CWENO_E_ARG, who + " too large for 32-bit coefficient offsets");
+    const uint64_t nq = (uint64_t)n_vars[i] * m->nc * es, nco = nq * m->nb;
+    if (cweno_abi::overlap(q[i], nq, coeffs[i], nco)) return fail(CWENO_E_ARG, who + ": q overlaps coeffs");
+    const cweno_abi::PackFootprint f = cweno_abi::pack_footprint(m, n_vars[i], f32);
+    if (!f.halo_ok)
+      return fail(CWENO_E_ARG, who + ": its block halos do not fit in LDS (reconstruct this mesh on its own)");
+    entries += f.entries;
+    items += f.items;
+    rq.push_back({m, q[i], coeffs[i], n_vars[i]});
+  }
+  if (entries > kNoAllocEntries || items > kNoAllocItems)
+    return fail(CWENO_E_ARG, "batch too large for the static scratch: " + std::to_string(entries) +
+                                 " variable blocks (at most 256) and " + std::to_string(items) +
+                                 " blocks of 256 cells (at most 65536)");
+  std::lock_guard<std::mutex> g(g_noalloc_mu);
+  NoAllocDevice& D = g_noalloc[dev];
+  if (!D.scratch) {
+    // set-up on this device's first call: kernel attributes, the array's address, the stage event
+    if (cweno_status st = cweno_abi::configure_device_kernels()) return st;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(CWENO_E_HIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    if (!D.staged && hipEventCreateWithFlags(&D.staged, hipEventDisableTiming) != hipSuccess)
+      return fail(CWENO_E_HIP, "event creation failed");
+    D.scratch = static_cast<char*>(ptr);
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  // the previous call's copy out of the host stage must be complete
+  hipError_t e = hipEventSynchronize(D.staged);
+  if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("hipEventSynchronize failed: ") + hipGetErrorString(e));
+  std::vector<cweno_abi::PackGroup> groups;
+  int n_entries = 0;
+  int64_t n_items = 0;
+  auto* h_items = reinterpret_cast<cweno::BatchItem*>(g_noalloc_stage + kNoAllocTable);
+  cweno_abi::pack_requests(rq.data(), (int)rq.size(), f32, g_noalloc_stage, h_items, groups, n_entries, n_items);
+  const size_t pb = f32 ? sizeof(cweno::KParams<float>) : sizeof(cweno::KParams<double>);
+  e = hipMemcpyAsync(D.scratch, g_noalloc_stage, (size_t)n_entries * pb, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(D.scratch + kNoAllocTable, h_items, (size_t)n_items * sizeof(cweno::BatchItem),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(D.staged, s);
+  if (e == hipSuccess)
+    e = cweno_abi::launch_packed(groups, f32, D.scratch,
+                                 reinterpret_cast<const cweno::BatchItem*>(D.scratch + kNoAllocTable), s);
+  if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("batched launch failed: ") + hipGetErrorString(e));
+  return CWENO_OK;
+}
