@@ -542,9 +542,8 @@ def measure_serving_full(torch, C, seconds, rate=2000.0, n_meshes=200, lo=2e3, h
         info = srv.mesh_info(ids[-1])
         foot += info["image_bytes"]
         raw.append((m if m.n_cells <= 60000 else None, d, M, m.n_cells, info["n_basis"]))
-        if k % 10 == 9:
-            log(f"serving full: registered {k + 1} meshes, {sum(r[3] for r in raw)} cells, "
-                f"{foot / 1e9:.1f} GB of FP32 images, {time.perf_counter() - t0:.0f} s")
+        log(f"serving full: registered {k + 1} meshes ({d}-D, M={M}, {m.n_cells} cells), "
+            f"{sum(r[3] for r in raw)} cells, {foot / 1e9:.1f} GB of FP32 images, {time.perf_counter() - t0:.0f} s")
     t_reg = time.perf_counter() - t0
     cells = sum(r[3] for r in raw)
     cv = [r[3] * nv for r in raw]
@@ -868,7 +867,7 @@ def main():
         res2 = measure(torch, C, m2, Q2, 3, 0.0, args.steps, args.warmup, "tri512 M3", 2,
                        keep_out="tri512" in only and not args.no_oracle_error)
         for tag in ("f64", "f32"):
-            with_traffic(res2[tag], tag, tag)
+            with_traffic(res2[tag], tag, "tri512_M3_nv9_" + tag)
         if "tri512" in only:
             extras["tri512_M3_nv9"] = {
                 "workload": "2-D M=3 (10 basis functions), 524,288 jittered periodic triangles (512x512x2), n_e=20, "

@@ -151,7 +151,10 @@ cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int
   p.binv32 = (float*)m->binv32.p;
   p.mask = (uint8_t*)m->mask.p;
   p.Np = m->Np;
-  for (int a = 0; a < 3; ++a) p.box[a] = m->box[a];
+  for (int a = 0; a < 3; ++a) {
+    p.box[a] = m->box[a];
+    p.ibox[a] = m->box[a] != 0.0 ? 1.0 / m->box[a] : 0.0;
+  }
   for (int t = 0; t < 5; ++t) p.lam[t] = m->lam[t];
   p.eps = m->eps;
   p.nc = m->nc;

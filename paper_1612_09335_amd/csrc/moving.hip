@@ -27,7 +27,10 @@ cweno::MParams<T> moving_params(const cweno_mesh* m, const double* vertices, int
   p.sig = (T*)sigma;
   p.om = (T*)omega;
   p.fault = fault;
-  for (int a = 0; a < 3; ++a) p.box[a] = m->box[a];
+  for (int a = 0; a < 3; ++a) {
+    p.box[a] = m->box[a];
+    p.ibox[a] = m->box[a] != 0.0 ? 1.0 / m->box[a] : 0.0;
+  }
   for (int s = 0; s < 5; ++s) p.lam[s] = m->lam[s];
   p.eps = m->eps;
   p.nc = m->nc;

@@ -86,6 +86,7 @@ struct MParams {
   uint8_t* mask;
   int64_t Np;
   double box[3];          // period per axis, 0 = none
+  double ibox[3];         // 1 / period per axis, 0 = none
   double lam[5];          // linear weights lambda_0 .. lambda_{D+1}
   double eps;
   int64_t nc;
@@ -190,8 +191,12 @@ __device__ __forceinline__ double seg_bcast(double x, int seg) {
 
 // ---------------------------------------------------------------- small dense algebra
 
-__device__ __forceinline__ double min_image_d(double d, double L) {
-  return L != 0.0 ? d - L * floor(d / L + 0.5) : d;
+// Minimum image of a difference d along an axis of period L (iL = 1/L; L = 0:
+// not periodic).  The product by the reciprocal decides the same image as a
+// quotient would except within rounding of half a period, which no stencil
+// spans.
+__device__ __forceinline__ double min_image_d(double d, double L, double iL) {
+  return L != 0.0 ? d - L * floor(d * iL + 0.5) : d;
 }
 
 // Inverse of a small dense matrix (Gauss-Jordan, partial pivoting); false if
@@ -377,7 +382,7 @@ __device__ __forceinline__ void cell_vertices(const MParams<T>& p, int64_t c, do
 #pragma unroll
   for (int v = 1; v <= D; ++v)
 #pragma unroll
-    for (int a = 0; a < D; ++a) X[v][a] = X[0][a] + min_image_d(X[v][a] - X[0][a], p.box[a]);
+    for (int a = 0; a < D; ++a) X[v][a] = X[0][a] + min_image_d(X[v][a] - X[0][a], p.box[a], p.ibox[a]);
 }
 
 template <int D>
@@ -461,12 +466,12 @@ void moving_kernel(MParams<T> p) {
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         const double dc = cj[a] - ci[a];
-        sh[a] = min_image_d(dc, p.box[a]) - dc;
+        sh[a] = min_image_d(dc, p.box[a], p.ibox[a]) - dc;
       }
       {   // the barycentre in the cell's frame, for the sector lanes
         double y[D];
 #pragma unroll
-        for (int b = 0; b < D; ++b) y[b] = ci[b] + min_image_d(cj[b] - ci[b], p.box[b]) - X0[b];
+        for (int b = 0; b < D; ++b) y[b] = ci[b] + min_image_d(cj[b] - ci[b], p.box[b], p.ibox[b]) - X0[b];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
           double t2 = 0.0;
@@ -616,7 +621,7 @@ void moving_kernel(MParams<T> p) {
           cell_vertices<D>(p, sj[a], X);
           barycentre<D>(X, cj);
 #pragma unroll
-          for (int b = 0; b < D; ++b) y[b] = ci[b] + min_image_d(cj[b] - ci[b], p.box[b]) - X0[b];
+          for (int b = 0; b < D; ++b) y[b] = ci[b] + min_image_d(cj[b] - ci[b], p.box[b], p.ibox[b]) - X0[b];
 #pragma unroll
           for (int r = 0; r < D; ++r) {
             double t = 0.0;
@@ -872,8 +877,9 @@ void moving_kernel(MParams<T> p) {
           om[s] *= lam[s];
           tot += om[s];
         }
+        const double itot = 1.0 / tot;
 #pragma unroll
-        for (int s = 0; s <= NS; ++s) om[s] /= tot;
+        for (int s = 0; s <= NS; ++s) om[s] *= itot;
       }
       T* o = p.out + (int64_t)v * NB * nc + i;
       o[0] = qiT;
