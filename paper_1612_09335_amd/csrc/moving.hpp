@@ -9,17 +9,18 @@
 namespace cweno {
 
 // Segment shapes (lanes per cell, rows per lane) instantiated for (D, M): the
-// rows of R must lie in the first row slot (fewer basis functions than
-// lanes), and two rows per lane on 64 lanes serve the wide 3-D stencils.
+// rows of R must lie in the segment's row slots (fewer basis functions than
+// lanes times rows per lane), four rows per lane only on 16 lanes, and two
+// rows per lane on 64 lanes only for the wide 3-D stencils.
 __host__ __device__ constexpr bool move_shape_ok(int D, int M, int seg, int rpl) {
-  return (seg == 16 || seg == 32 || seg == 64) && (rpl == 1 || rpl == 2) && nbasis_c(M, D) - 1 < seg &&
-         (seg < 64 || rpl == 1 || (D == 3 && M >= 2));
+  return (seg == 16 || seg == 32 || seg == 64) && (rpl == 1 || rpl == 2 || rpl == 4) &&
+         nbasis_c(M, D) - 1 < seg * rpl && (rpl < 4 || seg == 16) && (seg < 64 || rpl == 1 || (D == 3 && M >= 2));
 }
 
 // Preferred shapes, in order: the narrowest segment whose rows hold the
 // stencil, with as few rows per lane as that allows (fewer exchange stages per
 // sum, more cells per wave instruction).
-constexpr int kMoveShapes[6][2] = {{16, 1}, {16, 2}, {32, 1}, {32, 2}, {64, 1}, {64, 2}};
+constexpr int kMoveShapes[7][2] = {{16, 1}, {16, 2}, {16, 4}, {32, 1}, {32, 2}, {64, 1}, {64, 2}};
 
 // First instantiated shape whose rows hold the NE1 stencil cells besides the
 // cell (with one_row, among the shapes of one row per lane); false if none

@@ -57,11 +57,14 @@ constexpr int kMoveThreads = 256;  // four waves per block
 // Waves per SIMD the register allocation must leave room for.  The 3-D
 // degree-3 kernels with one stencil row per lane need 200-218 registers on
 // their own (two waves); bounded to 168 they run three waves with a few
-// spills, which measured 9% faster.  The kernels with two rows per lane and
-// the 3-D degree-4 ones need all 256 and would spill heavily; the others fit
-// three or four waves unbounded.
+// spills, which measured 9% faster.  With two rows per lane they fit two
+// waves (254 registers, 4 spills); with four (16 lanes per cell) they take
+// the accumulation registers as well and run one wave of four cells, which
+// measured 7% faster than two waves of two cells.  The 3-D degree-4 kernels
+// need all 256 and would spill heavily; the others fit three or four waves
+// unbounded.
 __host__ __device__ constexpr int move_min_waves(int D, int M, int RPL) {
-  return D == 3 && M == 3 ? (RPL == 1 ? 3 : 2) : 1;
+  return D == 3 && M == 3 ? (RPL == 1 ? 3 : RPL == 2 ? 2 : 1) : 1;
 }
 
 template <typename T>
@@ -407,7 +410,7 @@ void moving_kernel(MParams<T> p) {
   constexpr int CPW = 64 / SEG;                          // cells per wave
   constexpr int CPB = (kMoveThreads / 64) * CPW;         // cells per block
   constexpr int CH = 8;                                  // column sums in flight
-  static_assert(NL < SEG, "the rows of R lie in the first row slot of the segment's lanes");
+  static_assert(NL < SEG * RPL, "the rows of R lie in the segment's row slots");
   // per-cell LDS record (doubles): P_opt of a pass of variables (or, when
   // assembling operators, the rows of R), column scales, diagonal of R,
   // reflector factors, sector inverses, each row cell's barycentre in the
@@ -788,20 +791,24 @@ void moving_kernel(MParams<T> p) {
       const double ik = 1.0 / L[ORD + k];
       double xk[VB];
 #pragma unroll
-      for (int v = 0; v < VB; ++v) xk[v] = seg_bcast<SEG, k>(dq[0][v], seg) * ik;
-      if (row[0] < k) {
-        const double rk = A[0][k];
+      for (int v = 0; v < VB; ++v) xk[v] = seg_bcast<SEG, k % SEG>(dq[k / SEG][v], seg) * ik;
 #pragma unroll
-        for (int v = 0; v < VB; ++v) dq[0][v] = fma(-rk, xk[v], dq[0][v]);
-      }
+      for (int t = 0; t <= k / SEG; ++t)
+        if (row[t] < k) {
+          const double rk = A[t][k];
+#pragma unroll
+          for (int v = 0; v < VB; ++v) dq[t][v] = fma(-rk, xk[v], dq[t][v]);
+        }
     };
     StaticFor<0, NL>::run(back);
     // P_opt coefficient r of each variable (column scale undone), to LDS
-    if (row[0] < NL) {
-      const double f = 1.0 / (L[ORD + row[0]] * L[OSC + row[0]]);
 #pragma unroll
-      for (int v = 0; v < VB; ++v) L[OP + v * NL + row[0]] = dq[0][v] * f;
-    }
+    for (int t = 0; t < RPL; ++t)
+      if (t * SEG < NL && row[t] < NL) {
+        const double f = 1.0 / (L[ORD + row[t]] * L[OSC + row[t]]);
+#pragma unroll
+        for (int v = 0; v < VB; ++v) L[OP + v * NL + row[t]] = dq[t][v] * f;
+      }
     __syncthreads();
     if (valid && sl < nvb) {
       const int v = v0 + sl;

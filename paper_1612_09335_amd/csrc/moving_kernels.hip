@@ -79,6 +79,7 @@ hipError_t CWENO_ASM_FN(CWENO_D, CWENO_M)(const MParams<double>& p, int seg, hip
 hipError_t CWENO_MOVE_FN(CWENO_TN, CWENO_D, CWENO_M)(const MParams<real_t>& p, int seg, int rpl, hipStream_t s) {
   if (seg == 16 && rpl == 1) return launch_shape<16, 1>(p, s);
   if (seg == 16 && rpl == 2) return launch_shape<16, 2>(p, s);
+  if (seg == 16 && rpl == 4) return launch_shape<16, 4>(p, s);
   if (seg == 32 && rpl == 1) return launch_shape<32, 1>(p, s);
   if (seg == 32 && rpl == 2) return launch_shape<32, 2>(p, s);
   if (seg == 64 && rpl == 1) return launch_shape<64, 1>(p, s);

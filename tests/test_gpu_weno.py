@@ -1,11 +1,12 @@
 """GPU parity of the classical WENO kernel (the comparison scheme) against
 the oracle's WENO reconstruction: FP64 data-scaled coefficient error <= 1e-12
 at sampled cells (the scale: the largest |Q| over the cell's stencils); at
-degree 4 the bar is 1e-11, derived from the arithmetic: the one-sided cone
+degree 4 the bar is 3e-12, derived from the arithmetic: the one-sided cone
 stencils' column-scaled least-squares matrices reach condition numbers of
 about 8e3 (against 2e2 for the central stencils), and two backward-stable FP64
-solvers (Householder on the host, SVD in the oracle) then differ by up to
-about u * kappa ~ 1e-12 of the data scale;
+solvers (Householder on the host, SVD in the oracle) then differ by up to a
+small multiple of u * kappa ~ 9e-13 of the data scale (measured on the degree-4
+case below: 1.3e-12);
 coefficient 0 bit for bit, cell counts leaving the last workgroup ragged and
 variable counts leaving the last variable block partly empty; end to end,
 the reconstruction of the exact averages of a degree-M polynomial evaluated
@@ -52,7 +53,7 @@ def test_weno_against_oracle(name, mk, M, nv, lam):
     scale = np.array([[np.abs(Q[v, s[s >= 0]]).max() for s in st.reshape(len(idx), -1)] for v in range(nv)])
     err = (np.abs(got[:, :, idx] - ref["coeffs"]) / scale[:, None, :]).max()
     print(f"[gpu weno]   data-scaled error {err:.3e}", flush=True)
-    assert err <= (1e-11 if M == 4 else 1e-12)
+    assert err <= (3e-12 if M == 4 else 1e-12)
 
 
 def test_weno_reproduces_polynomials_and_refuses_other_forms():
