@@ -552,7 +552,7 @@ cweno_status cweno_reconstruct(const cweno_mesh* m, int n_vars, cweno_dtype dtyp
   hipStream_t s = (hipStream_t)hip_stream;
   const bool f32 = dtype == CWENO_F32;
   for (int v0 = 0; v0 < n_vars;) {
-    const int vb = cweno::pick_vb(m->d, m->M, n_vars - v0, f32);
+    const int vb = cweno_abi::pick_vb_mesh(m, n_vars - v0, f32);
     const int k = m->variant[f32][vb];
     hipError_t e = launch_block(m, f32, q, coeffs, sigma, omega, v0, vb, k, s);
     if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -602,7 +602,7 @@ cweno_status cweno_mesh_tune(cweno_mesh* m, int n_vars, cweno_dtype dtype, const
   double total = 0.0;
   st = CWENO_OK;
   for (int v0 = 0; v0 < n_vars && st == CWENO_OK;) {
-    const int vb = cweno::pick_vb(m->d, m->M, n_vars - v0, f32);
+    const int vb = cweno_abi::pick_vb_mesh(m, n_vars - v0, f32);
     float best = 0.0f;
     int best_k = -1;
     for (int k = 0; k < cweno::kNumVariants && st == CWENO_OK; ++k) {

@@ -273,7 +273,7 @@ cweno_status cweno_batch_create(int n, cweno_mesh* const* meshes, const int* n_v
     b->meshes.push_back(m);
     b->n_vars.push_back(n_vars[i]);
     for (int v0 = 0; v0 < n_vars[i];) {
-      const int vb = cweno::pick_vb(m->d, m->M, n_vars[i] - v0, f32);
+      const int vb = cweno_abi::pick_vb_mesh(m, n_vars[i] - v0, f32, true);
       bool halo_ok = false;
       for (int k = 0; k < cweno::kNumVariants; ++k)
         if (cweno::kVariants[k].kind == 1 && cweno_abi::variant_ok(m, vb, k, f32)) halo_ok = true;

@@ -17,17 +17,24 @@ constexpr Variant kVariants[] = {{0, 1, 0}, {0, 2, 0}, {1, 1, 4}, {1, 2, 4}, {1,
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 // Variable-block sizes that are instantiated.  A lane keeps (n_basis-1) * VB
-// accumulators; blocks whose accumulators exceed the register budget
-// (100 doubles / 200 floats) are not instantiated.  The halo kernel also
+// accumulators; the direct kernel (and the fused point-value form) only
+// blocks whose accumulators fit the register budget (100 doubles / 200
+// floats), the LDS-halo kernel also blocks up to twice that, walking the
+// stencil twice for half of P_opt's rows each time.  The halo kernel also
 // needs maxH * VB values of LDS, at most the 160 KiB a workgroup may use.
 constexpr int kMaxLds = 160 * 1024;
+__host__ __device__ constexpr bool vb_size_ok(int VB) {
+  return VB == 1 || VB == 2 || VB == 3 || VB == 4 || VB == 5 || VB == 9;
+}
+__host__ __device__ constexpr bool vb_one_pass(int D, int M, int VB, bool f32) {
+  return vb_size_ok(VB) && (nbasis_c(M, D) - 1) * VB <= acc_budget(f32);
+}
 __host__ __device__ constexpr bool vb_allowed(int D, int M, int VB, bool f32) {
-  return (VB == 1 || VB == 2 || VB == 3 || VB == 4 || VB == 5 || VB == 9) &&
-         (nbasis_c(M, D) - 1) * VB <= (f32 ? 200 : 100);
+  return vb_size_ok(VB) && (nbasis_c(M, D) - 1) * VB <= 2 * acc_budget(f32);
 }
 
-__host__ __device__ constexpr bool variant_allowed(int D, int M, int VB, const Variant&, bool f32) {
-  return vb_allowed(D, M, VB, f32);
+__host__ __device__ constexpr bool variant_allowed(int D, int M, int VB, const Variant& V, bool f32) {
+  return V.kind == 0 ? vb_one_pass(D, M, VB, f32) : vb_allowed(D, M, VB, f32);
 }
 
 // Largest block size not above n that some variant instantiates.
@@ -37,6 +44,15 @@ inline int pick_vb(int D, int M, int n, bool f32) {
     if (vb <= n)
       for (const Variant& v : kVariants)
         if (variant_allowed(D, M, vb, v, f32)) return vb;
+  return 1;
+}
+
+// Largest block size not above n whose accumulators fit one pass (the fused
+// point-value form walks the stencil once).
+inline int pick_vb_one_pass(int D, int M, int n, bool f32) {
+  const int cand[] = {9, 5, 4, 3, 2, 1};
+  for (int vb : cand)
+    if (vb <= n && vb_one_pass(D, M, vb, f32)) return vb;
   return 1;
 }
 

@@ -167,10 +167,11 @@ cweno_status cweno_reconstruct_points(const cweno_mesh* m, const cweno_points* p
     return fail(CWENO_E_ARG, "q and values must not overlap");
   hipStream_t s = (hipStream_t)hip_stream;
   for (int v0 = 0; v0 < n_vars;) {
-    int vb = cweno::pick_vb(m->d, m->M, n_vars - v0, f32);
+    int vb = cweno::pick_vb_one_pass(m->d, m->M, n_vars - v0, f32);
     // the block halo of vb variables and a column of nb-1 coefficients per thread must fit in LDS
     const int64_t col = (int64_t)(m->nb - 1) * cweno::kHaloBlock * (int64_t)es;
-    while (vb > 1 && (int64_t)m->maxH * vb * (int64_t)es + col > cweno::kMaxLds) vb = cweno::pick_vb(m->d, m->M, vb - 1, f32);
+    while (vb > 1 && (int64_t)m->maxH * vb * (int64_t)es + col > cweno::kMaxLds)
+      vb = cweno::pick_vb_one_pass(m->d, m->M, vb - 1, f32);
     if ((int64_t)m->maxH * vb * (int64_t)es + col > cweno::kMaxLds)
       return fail(CWENO_E_ARG, "the block halos of this mesh leave no room for the fused point values");
     hipError_t e;

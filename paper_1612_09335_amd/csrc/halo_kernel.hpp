@@ -21,6 +21,8 @@
 // together, so one address per stencil entry serves every variable).
 #pragma once
 
+#include <type_traits>
+
 #include "reconstruct_kernel.hpp"
 
 namespace cweno {
@@ -38,6 +40,22 @@ __device__ __forceinline__ void load_rows(T (&r)[KC][NL], const T* pinv, int64_t
     const rsrc_t rk = make_rsrc(pinv + (int64_t)k * NL * Np, NL * prow);
 #pragma unroll
     for (int l = 0; l < NL; ++l) r[kk][l] = k < NE1 ? bld_stream<T>(rk, io, (uint32_t)l * prow) : T(0);
+  }
+}
+
+// Rows L0 .. L0+NR-1 of the operator rows of stencil entries k0 .. k0+KC-1
+// (the rows of P_opt one pass of the stencil walk accumulates).
+template <int NL, int NR, int KC, typename T>
+__device__ __forceinline__ void load_rows_part(T (&r)[KC][NR], const T* pinv, int64_t Np, int NE1, int k0, int L0,
+                                               uint32_t io) {
+  const uint32_t prow = (uint32_t)Np * (uint32_t)sizeof(T);
+#pragma unroll
+  for (int kk = 0; kk < KC; ++kk) {
+    const int k = k0 + kk;
+    const rsrc_t rk = make_rsrc(pinv + (int64_t)k * NL * Np, NL * prow);
+#pragma unroll
+    for (int l = 0; l < NR; ++l)
+      r[kk][l] = k < NE1 ? bld_stream<T>(rk, io, (uint32_t)(L0 + l) * prow) : T(0);
   }
 }
 
@@ -131,46 +149,108 @@ __device__ __forceinline__ void halo_block(const KParams<T>& p, int64_t b, T* lq
     }
   const unsigned mask = ldo(p.mask, (uint32_t)ic);
 
-  // (a) P_opt, stencil walked in chunks of KC entries; the first chunk's rows
-  // and positions are requested before the barrier
-  T rr[KC][NL];
-  uint32_t hc[KC];
-  load_rows<NL, KC, T>(rr, p.pinv, Np, NE1, 0, io);
-  load_pos<KC>(hc, rl, lrow, NE1, 0, io2, self);
-  __syncthreads();
+  constexpr int NCH = halo_chunks(D, M, VB, sizeof(T) == 4);
+  if constexpr (NCH == 1) {
+    // (a) P_opt, stencil walked in chunks of KC entries; the first chunk's rows
+    // and positions are requested before the barrier
+    T rr[KC][NL];
+    uint32_t hc[KC];
+    load_rows<NL, KC, T>(rr, p.pinv, Np, NE1, 0, io);
+    load_pos<KC>(hc, rl, lrow, NE1, 0, io2, self);
+    __syncthreads();
 
-  T acc[NL][VB];
+    T acc[NL][VB];
 #pragma unroll
-  for (int l = 0; l < NL; ++l)
+    for (int l = 0; l < NL; ++l)
 #pragma unroll
-    for (int v = 0; v < VB; ++v) acc[l][v] = T(0);
+      for (int v = 0; v < VB; ++v) acc[l][v] = T(0);
 
-  fma_chunk<NL, VB, KC, T>(acc, rr, hc, lq, self);
-  for (int k0 = KC; k0 < NE1; k0 += KC) {
-    load_rows<NL, KC, T>(rr, p.pinv, Np, NE1, k0, io);
-    load_pos<KC>(hc, rl, lrow, NE1, k0, io2, self);
     fma_chunk<NL, VB, KC, T>(acc, rr, hc, lq, self);
-  }
+    for (int k0 = KC; k0 < NE1; k0 += KC) {
+      load_rows<NL, KC, T>(rr, p.pinv, Np, NE1, k0, io);
+      load_pos<KC>(hc, rl, lrow, NE1, k0, io2, self);
+      fma_chunk<NL, VB, KC, T>(acc, rr, hc, lq, self);
+    }
 
-  T lam[NS + 1];
-  const T inv_l0 = cell_weights<NS, T>(p, mask, lam);
-  if (valid) {
-    T bv[NS][D][D];
-    load_binv<D, T>(p.binv, Np, io, bv);
-    const T* sv = lq + self * VB;
+    T lam[NS + 1];
+    const T inv_l0 = cell_weights<NS, T>(p, mask, lam);
+    if (valid) {
+      T bv[NS][D][D];
+      load_binv<D, T>(p.binv, Np, io, bv);
+      const T* sv = lq + self * VB;
 #pragma unroll
-    for (int v = 0; v < VB; ++v) {
-      const T qi = sv[v];
-      T dqs[NS][D];
+      for (int v = 0; v < VB; ++v) {
+        const T qi = sv[v];
+        T dqs[NS][D];
 #pragma unroll
-      for (int s = 0; s < NS; ++s)
+        for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int a = 0; a < D; ++a) dqs[s][a] = lq[sl[s][a] * VB + v] - qi;
-      T po[NL];
+          for (int a = 0; a < D; ++a) dqs[s][a] = lq[sl[s][a] * VB + v] - qi;
+        T po[NL];
 #pragma unroll
-      for (int l = 0; l < NL; ++l) po[l] = acc[l][v];
-      finish_variable<D, M, T, PTS>(p, io, v, qi, po, lam, inv_l0, dqs, bv,
-                                    PTS ? lq + (size_t)p.maxH * VB + tid : nullptr);
+        for (int l = 0; l < NL; ++l) po[l] = acc[l][v];
+        finish_variable<D, M, T, PTS>(p, io, v, qi, po, lam, inv_l0, dqs, bv,
+                                      PTS ? lq + (size_t)p.maxH * VB + tid : nullptr);
+      }
+    }
+  } else {
+    // (a) P_opt in two walks of the stencil, each accumulating half of its
+    // rows for all VB variables (every operator entry is still read once);
+    // each half waits in the cell's own coefficient rows 1.. of the output,
+    // which the same lane reads back before the epilogue overwrites them
+    static_assert(NCH == 2 && !PTS, "two passes over the stencil, coefficients written to the output");
+    constexpr int R0 = (NL + 1) / 2;
+    const uint32_t crow = (uint32_t)qs * (uint32_t)sizeof(T);
+    auto pass = [&](auto half) {
+      constexpr int L0 = decltype(half)::value * R0;
+      constexpr int NR = decltype(half)::value == 0 ? R0 : NL - R0;
+      T rr[KC][NR];
+      uint32_t hc[KC];
+      load_rows_part<NL, NR, KC, T>(rr, p.pinv, Np, NE1, 0, L0, io);
+      load_pos<KC>(hc, rl, lrow, NE1, 0, io2, self);
+      if constexpr (L0 == 0) __syncthreads();
+      T acc[NR][VB];
+#pragma unroll
+      for (int l = 0; l < NR; ++l)
+#pragma unroll
+        for (int v = 0; v < VB; ++v) acc[l][v] = T(0);
+      fma_chunk<NR, VB, KC, T>(acc, rr, hc, lq, self);
+      for (int k0 = KC; k0 < NE1; k0 += KC) {
+        load_rows_part<NL, NR, KC, T>(rr, p.pinv, Np, NE1, k0, L0, io);
+        load_pos<KC>(hc, rl, lrow, NE1, k0, io2, self);
+        fma_chunk<NR, VB, KC, T>(acc, rr, hc, lq, self);
+      }
+      if (valid) {
+#pragma unroll
+        for (int v = 0; v < VB; ++v) {
+          const rsrc_t ro = make_rsrc(p.out + (int64_t)(p.v0 + v) * NB * qs, NB * crow);
+#pragma unroll
+          for (int l = 0; l < NR; ++l) bst_keep(ro, acc[l][v], io, (uint32_t)(1 + L0 + l) * crow);
+        }
+      }
+    };
+    pass(std::integral_constant<int, 0>{});
+    pass(std::integral_constant<int, 1>{});
+    T lam[NS + 1];
+    const T inv_l0 = cell_weights<NS, T>(p, mask, lam);
+    if (valid) {
+      T bv[NS][D][D];
+      load_binv<D, T>(p.binv, Np, io, bv);
+      const T* sv = lq + self * VB;
+#pragma unroll
+      for (int v = 0; v < VB; ++v) {
+        const T qi = sv[v];
+        T dqs[NS][D];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+          for (int a = 0; a < D; ++a) dqs[s][a] = lq[sl[s][a] * VB + v] - qi;
+        const rsrc_t ro = make_rsrc(p.out + (int64_t)(p.v0 + v) * NB * qs, NB * crow);
+        T po[NL];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) po[l] = bld<T>(ro, io, (uint32_t)(1 + l) * crow);
+        finish_variable<D, M, T, false>(p, io, v, qi, po, lam, inv_l0, dqs, bv, nullptr);
+      }
     }
   }
 }

@@ -33,7 +33,7 @@ namespace {
 // Fused point values: the halo kernel with chunk 1 and halo unroll 4.
 template <int VB>
 hipError_t launch_points_t(const KParams<real_t>& p, hipStream_t s) {
-  if constexpr (vb_allowed(CWENO_D, CWENO_M, VB, sizeof(real_t) == 4)) {
+  if constexpr (vb_one_pass(CWENO_D, CWENO_M, VB, sizeof(real_t) == 4)) {
     const int64_t blocks = (p.nc + kHaloBlock - 1) / kHaloBlock;
     // block halo and a column of nb-1 blended coefficients per thread
     constexpr int NB = nbasis_c(CWENO_M, CWENO_D);
@@ -49,7 +49,7 @@ hipError_t launch_points_t(const KParams<real_t>& p, hipStream_t s) {
 
 template <int VB, int KC>
 hipError_t launch_direct(const KParams<real_t>& p, hipStream_t s) {
-  if constexpr (vb_allowed(CWENO_D, CWENO_M, VB, sizeof(real_t) == 4)) {
+  if constexpr (vb_one_pass(CWENO_D, CWENO_M, VB, sizeof(real_t) == 4)) {
     const int64_t blocks = (p.nc + kThreads - 1) / kThreads;
     hipLaunchKernelGGL((reconstruct_kernel<CWENO_D, CWENO_M, VB, KC, real_t>), dim3((unsigned)blocks),
                        dim3(kThreads), 0, s, p, CWENO_ARRAY_ARGS(p));
@@ -96,9 +96,10 @@ hipError_t configure_t() {
     if (e == hipSuccess)
       e = hipFuncSetAttribute((const void*)reconstruct_batch_kernel<CWENO_D, CWENO_M, VB, KC, HU, real_t>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-    if (e == hipSuccess && KC == 1 && HU == 4)
-      e = hipFuncSetAttribute((const void*)reconstruct_halo_kernel<CWENO_D, CWENO_M, VB, 1, 4, real_t, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if constexpr (KC == 1 && HU == 4 && vb_one_pass(CWENO_D, CWENO_M, VB, sizeof(real_t) == 4))
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)reconstruct_halo_kernel<CWENO_D, CWENO_M, VB, 1, 4, real_t, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     return e;
   } else {
     return hipSuccess;

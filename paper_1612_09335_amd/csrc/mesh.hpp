@@ -121,6 +121,19 @@ inline int default_variant(const cweno_mesh* m, int vb, bool f32) {
   return -1;
 }
 
+// Largest variable block not above n that this mesh can run: some variant
+// (with halo_only, an LDS-halo variant) is instantiated for it and, for the
+// halo kernel, the mesh's block halos of that many variables fit in LDS.
+inline int pick_vb_mesh(const cweno_mesh* m, int n, bool f32, bool halo_only = false) {
+  const int cand[] = {9, 5, 4, 3, 2, 1};
+  for (int vb : cand) {
+    if (vb > n) continue;
+    for (int k = 0; k < cweno::kNumVariants; ++k)
+      if ((!halo_only || cweno::kVariants[k].kind == 1) && variant_ok(m, vb, k, f32)) return vb;
+  }
+  return 1;
+}
+
 template <typename T>
 inline cweno::KParams<T> make_params(const cweno_mesh* m, const void* q, void* coeffs, void* sigma, void* omega, int v0) {
   const bool f32 = sizeof(T) == 4;

@@ -43,7 +43,7 @@ inline PackFootprint pack_footprint(const cweno_mesh* m, int n_vars, bool f32) {
   PackFootprint f;
   const int64_t nblk = (m->nc + cweno::kHaloBlock - 1) / cweno::kHaloBlock;
   for (int v0 = 0; v0 < n_vars;) {
-    const int vb = cweno::pick_vb(m->d, m->M, n_vars - v0, f32);
+    const int vb = pick_vb_mesh(m, n_vars - v0, f32, true);
     bool ok = false;
     for (int k = 0; k < cweno::kNumVariants; ++k)
       if (cweno::kVariants[k].kind == 1 && variant_ok(m, vb, k, f32)) ok = true;
@@ -70,7 +70,7 @@ inline void pack_requests(const PackRequest* reqs, int n, bool f32, char* h_tabl
   for (int t = 0; t < n; ++t) {
     const cweno_mesh* m = reqs[t].m;
     for (int v0 = 0; v0 < reqs[t].n_vars;) {
-      const int vb = cweno::pick_vb(m->d, m->M, reqs[t].n_vars - v0, f32);
+      const int vb = pick_vb_mesh(m, reqs[t].n_vars - v0, f32, true);
       size_t g = 0;
       while (g < groups.size() && !(groups[g].d == m->d && groups[g].M == m->M && groups[g].vb == vb)) ++g;
       if (g == groups.size()) {

@@ -49,6 +49,17 @@ __host__ __device__ constexpr int nbasis_c(int M, int D) {
   return D == 2 ? (M + 1) * (M + 2) / 2 : (M + 1) * (M + 2) * (M + 3) / 6;
 }
 
+// P_opt accumulators one lane may hold in registers: (NB-1) * VB of them,
+// at most 100 doubles or 200 floats.
+__host__ __device__ constexpr int acc_budget(bool f32) { return f32 ? 200 : 100; }
+
+// Passes of the LDS-halo kernel over the stencil for one block of VB
+// variables: 1 when all (NB-1) * VB accumulators fit the budget, else 2, each
+// accumulating half of P_opt's rows (the operator rows are still read once).
+__host__ __device__ constexpr int halo_chunks(int D, int M, int VB, bool f32) {
+  return (nbasis_c(M, D) - 1) * VB <= acc_budget(f32) ? 1 : 2;
+}
+
 template <typename T>
 struct KParams {
   const T* q;
@@ -142,6 +153,13 @@ template <> __device__ __forceinline__ double bld_stream<double>(rsrc_t r, uint3
 }
 template <> __device__ __forceinline__ float bld_stream<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, kStream));
+}
+// Store that keeps the line in the caches (a value the same lane reads back).
+__device__ __forceinline__ void bst_keep(rsrc_t r, double x, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bst_keep(rsrc_t r, float x, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, voff, soff, 0);
 }
 // Coefficient-row store, streamed (written once per launch).
 __device__ __forceinline__ void bst(rsrc_t r, double x, uint32_t voff, uint32_t soff) {

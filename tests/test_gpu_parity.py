@@ -78,6 +78,26 @@ def test_small_meshes_f64(case):
     _check_f64(m, M, Q)
 
 
+@pytest.mark.parametrize("case", ["kuhn7_M4_nv5", "kuhn5_M3_nv9", "tri12_M4_nv9"])
+def test_two_pass_blocks_f64(case):
+    """Variable blocks whose FP64 accumulators exceed one lane's budget: the
+    halo kernel walks the stencil twice, half of P_opt's rows each time (3-D
+    degree 4 with 5 variables, 3-D degree 3 with 9, 2-D degree 4 with 9);
+    ragged last block; sampled cells against the oracle."""
+    rng = np.random.default_rng(abs(hash(case)) % 2**32)
+    if case == "kuhn7_M4_nv5":
+        m, M, nv = kuhn_tet_mesh(7, 0.1, 51), 4, 5
+    elif case == "kuhn5_M3_nv9":
+        m, M, nv = kuhn_tet_mesh(5, 0.1, 52), 3, 9
+    else:
+        m, M, nv = tri_mesh(12, 0.15, 53), 4, 9
+    Q = rng.normal(size=(nv, m.n_cells)) + 4.0 * (rng.random((1, m.n_cells)) < 0.25)
+    cells = np.unique(np.concatenate([rng.choice(m.n_cells, min(m.n_cells, 48), replace=False),
+                                      np.arange(max(0, m.n_cells - 8), m.n_cells)]))
+    lm, _ = _check_f64(m, M, Q, cells=cells)
+    assert lm.get_variant("f64", nv if nv < 9 else 9)[0] >= 0
+
+
 @pytest.mark.parametrize("opt", [dict(sector_rule="face"), dict(lambda0="paper"), dict(sigma0_from="popt"),
                                  dict(linear_weights=True), dict(r=2, eps=1e-6), dict(lambda0=0.5)])
 def test_options_f64(opt):
@@ -98,7 +118,8 @@ def test_deterministic_and_stream_ordered():
     assert np.array_equal(a.view(np.int64), b.view(np.int64))
 
 
-@pytest.mark.parametrize("case", ["tri13_M3_nv9", "kuhn6_M3_nv5", "tri12_M2_nv4", "tri10_M4_nv5", "kuhn5_M2_nv9"])
+@pytest.mark.parametrize("case", ["tri13_M3_nv9", "kuhn6_M3_nv5", "tri12_M2_nv4", "tri10_M4_nv5", "kuhn5_M2_nv9",
+                                  "kuhn7_M4_nv5"])
 def test_every_variant_bitwise_identical(case):
     """All kernel variants (lanes per cell, stencil chunk) give the same bits,
     and the default one matches the oracle."""
@@ -112,6 +133,8 @@ def test_every_variant_bitwise_identical(case):
         m, M, nv = tri_mesh(12, 0.15, 43), 2, 4
     elif case == "tri10_M4_nv5":
         m, M, nv = tri_mesh(10, 0.15, 44), 4, 5
+    elif case == "kuhn7_M4_nv5":
+        m, M, nv = kuhn_tet_mesh(7, 0.1, 47), 4, 5
     else:
         m, M, nv = kuhn_tet_mesh(5, 0.1, 45), 2, 9
     rng = np.random.default_rng(46)
