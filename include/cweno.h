@@ -430,8 +430,9 @@ cweno_status cweno_batch_run_noalloc(int n, const cweno_mesh* const* meshes, con
  *                        A scheduler thread and a completion thread start here.
  * cweno_server_register  host precompute of a mesh (arguments as for
  *                        cweno_mesh_create; opt->ops and HOST_ONLY are set by
- *                        the server) and one pinned host image of its whole
- *                        device layout.  *mesh_id receives its id.
+ *                        the server) and one host image of its whole device
+ *                        layout (pinned memory up to the pinned limit,
+ *                        pageable beyond it).  *mesh_id receives its id.
  *                        CWENO_E_BUDGET if the image alone exceeds the budget.
  * cweno_server_register_mesh  the same from a mesh built with CWENO_FLAG_HOST_ONLY
  *                        (its precompute is reused; the caller keeps ownership
@@ -463,6 +464,11 @@ cweno_status cweno_batch_run_noalloc(int n, const cweno_mesh* const* meshes, con
  *                        cweno_server_reset_stats.  Any pointer may be NULL.
  * cweno_server_set_batch requests one launch may carry (1..512; 1 = every
  *                        request launched on its own).
+ * cweno_server_set_pinned_limit  bytes of mesh images registered from now on
+ *                        that may be kept in pinned host memory (default
+ *                        32 GiB); images beyond it are pageable (slower
+ *                        uploads).  Pinned memory is a limited resource of the
+ *                        host, which the runtime's own pageable copies need too.
  * cweno_server_launch_stats  launches started, requests that shared a launch
  *                        with others, the most requests in one launch (since
  *                        creation or the last reset), and the tickets the
@@ -489,6 +495,7 @@ cweno_status cweno_server_stats(cweno_server* server, double* p50_s, double* p99
                                 int64_t* completed, int64_t* evictions, int64_t* uploads, int64_t* upload_bytes);
 cweno_status cweno_server_reset_stats(cweno_server* server);
 cweno_status cweno_server_set_batch(cweno_server* server, int max_batch);
+cweno_status cweno_server_set_pinned_limit(cweno_server* server, int64_t bytes);
 cweno_status cweno_server_launch_stats(cweno_server* server, int64_t* launches, int64_t* shared_requests,
                                        int64_t* largest_launch, int64_t* tickets_held);
 cweno_status cweno_server_pause(cweno_server* server, int paused);

@@ -34,8 +34,8 @@ SYMBOLS = ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_
            "cweno_mesh_tune", "cweno_batch_create", "cweno_batch_run", "cweno_batch_info", "cweno_batch_group",
            "cweno_batch_destroy", "cweno_batch_run_noalloc", "cweno_server_create", "cweno_server_register", "cweno_server_register_mesh",
            "cweno_server_mesh_info", "cweno_server_submit", "cweno_server_poll", "cweno_server_wait", "cweno_server_cancel",
-           "cweno_server_stats", "cweno_server_reset_stats", "cweno_server_set_batch", "cweno_server_launch_stats",
-           "cweno_server_pause", "cweno_server_destroy")
+           "cweno_server_stats", "cweno_server_reset_stats", "cweno_server_set_batch", "cweno_server_set_pinned_limit",
+           "cweno_server_launch_stats", "cweno_server_pause", "cweno_server_destroy")
 
 
 class CwenoError(RuntimeError):
@@ -112,6 +112,7 @@ def _load():
     lib.cweno_server_stats.argtypes = [vp, dp, dp, dp, i64p, i64p, i64p, i64p]
     lib.cweno_server_reset_stats.argtypes = [vp]
     lib.cweno_server_set_batch.argtypes = [vp, ctypes.c_int]
+    lib.cweno_server_set_pinned_limit.argtypes = [vp, i64]
     lib.cweno_server_launch_stats.argtypes = [vp, i64p, i64p, i64p, i64p]
     lib.cweno_server_pause.argtypes = [vp, ctypes.c_int]
     lib.cweno_server_destroy.argtypes = [vp]
@@ -123,7 +124,8 @@ def _load():
                  "cweno_server_create", "cweno_server_register", "cweno_server_register_mesh",
                  "cweno_server_mesh_info", "cweno_server_submit",
                  "cweno_server_poll", "cweno_server_wait", "cweno_server_cancel", "cweno_server_stats",
-                 "cweno_server_reset_stats", "cweno_server_set_batch", "cweno_server_launch_stats",
+                 "cweno_server_reset_stats", "cweno_server_set_batch", "cweno_server_set_pinned_limit",
+                 "cweno_server_launch_stats",
                  "cweno_server_pause", "cweno_server_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
@@ -519,6 +521,10 @@ class Server:
 
     def reset_stats(self):
         _check(lib.cweno_server_reset_stats(self._h))
+
+    def set_pinned_limit(self, nbytes: int):
+        """Bytes of mesh images registered from now on that may be pinned (the rest pageable)."""
+        _check(lib.cweno_server_set_pinned_limit(self._h, int(nbytes)))
 
     def set_batch(self, max_batch: int):
         """Requests one launch may carry (1: every request launched on its own)."""

@@ -1,10 +1,12 @@
-// Serving loop: registered meshes whose operators live in pinned host memory
-// and move in and out of HBM under a byte budget, with reconstruction
-// requests batched as they arrive.
+// Serving loop: registered meshes whose operators live in host memory and
+// move in and out of HBM under a byte budget, with reconstruction requests
+// batched as they arrive.
 //
-// * Registration runs the host precompute once and keeps one pinned host
-//   image of the mesh's whole device layout (operators in the server's
-//   precision, index tables, block halos), so that residency is one copy.
+// * Registration runs the host precompute once and keeps one host image of
+//   the mesh's whole device layout (operators in the server's precision,
+//   index tables, block halos), so that residency is one copy.  Images are
+//   pinned up to the server's pinned limit (default 32 GiB) and pageable
+//   beyond it.
 // * HBM: one arena of `budget` bytes, allocated when the server is created;
 //   meshes are placed first-fit (256-byte granules) and the least recently
 //   used mesh with no request in flight is evicted when a placement fails.
@@ -31,6 +33,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -105,13 +108,21 @@ struct Layout {
 struct SMesh {
   std::unique_ptr<cweno_mesh> m;   // metadata, tables, kernel variants
   Layout lay;
-  void* image = nullptr;           // pinned host copy of the device image
+  void* image = nullptr;           // host copy of the device image
+  bool pinned = true;              // image in pinned memory (else pageable: slower uploads)
   bool resident = false;
   size_t off = 0;                  // arena offset while resident
   hipEvent_t ready = nullptr;      // the latest upload has completed
   int pins = 0;                    // admitted requests not yet complete
   uint64_t last_use = 0;
 };
+
+void free_image(SMesh& sm) {
+  if (!sm.image) return;
+  if (sm.pinned) (void)hipHostFree(sm.image);
+  else std::free(sm.image);
+  sm.image = nullptr;
+}
 
 enum ReqState { kQueued = 0, kRunning = 1, kDone = 2, kCancelled = 3, kFailed = 4 };
 
@@ -152,6 +163,8 @@ struct cweno_server {
   std::vector<hipStream_t> comp;
   int next_stream = 0;
   std::vector<std::unique_ptr<SMesh>> meshes;
+  size_t pin_limit = size_t(32) << 30;      // pinned image bytes at most (the rest pageable)
+  size_t pinned_bytes = 0;
   std::unordered_map<int64_t, Req> reqs;   // element addresses survive rehashing
   std::deque<int64_t> queue;
   std::vector<Launch> running;
@@ -247,7 +260,7 @@ hipError_t cweno_server::launch_lone(const Req& r, hipStream_t s) {
   const cweno_mesh* m = meshes[r.mesh]->m.get();
   hipError_t e = hipSuccess;
   for (int v0 = 0; v0 < r.n_vars && e == hipSuccess;) {
-    const int vb = cweno::pick_vb(m->d, m->M, r.n_vars - v0, f32);
+    const int vb = cweno_abi::pick_vb_mesh(m, r.n_vars - v0, f32);
     e = cweno_abi::launch_block(m, f32, r.q, r.coeffs, nullptr, nullptr, v0, vb, m->variant[f32][vb], s);
     v0 += vb;
   }
@@ -445,7 +458,7 @@ cweno_server::~cweno_server() {
     if (e) (void)hipEventDestroy(e);
   for (auto& sm : meshes) {
     if (sm->ready) (void)hipEventDestroy(sm->ready);
-    if (sm->image) (void)hipHostFree(sm->image);
+    free_image(*sm);
   }
   if (arena_base) (void)hipFree(arena_base);
   if (d_slots) (void)hipFree(d_slots);
@@ -482,8 +495,19 @@ cweno_status build_image(cweno_server* srv, SMesh& sm) {
   L.lidx = place(m->maxH > 0 ? h.lidx.size() * 2 : 0);
   L.total = at;
   if (L.total > srv->budget) return fail(CWENO_E_BUDGET, "mesh larger than the server's HBM budget");
-  if (hipHostMalloc(&sm.image, L.total, hipHostMallocDefault) != hipSuccess)
-    return fail(CWENO_E_NOMEM, "pinned host allocation failed");
+  // pinned memory up to the server's pinned limit (uploads at full bus speed),
+  // pageable memory beyond it: the images of a large registered set can
+  // exceed what the host may pin, and the runtime's own copies of pageable
+  // memory need pinned staging memory that must stay available
+  sm.pinned = srv->pinned_bytes + L.total <= srv->pin_limit &&
+              hipHostMalloc(&sm.image, L.total, hipHostMallocDefault) == hipSuccess;
+  if (sm.pinned) {
+    srv->pinned_bytes += L.total;
+  } else {
+    (void)hipGetLastError();
+    sm.image = std::malloc(L.total);
+    if (!sm.image) return fail(CWENO_E_NOMEM, "host allocation of the mesh image failed");
+  }
   char* img = static_cast<char*>(sm.image);
   if (srv->f32) {
     copy_rows<float>(op.pinv, img + L.pinv);
@@ -562,7 +586,7 @@ cweno_status adopt(cweno_server* s, cweno_mesh* raw, int64_t* mesh_id) {
   sm->m.reset(raw);
   cweno_mesh* m = raw;
   if (cweno_status st = build_image(s, *sm)) {
-    if (sm->image) (void)hipHostFree(sm->image);
+    free_image(*sm);
     return st;
   }
   // the image holds everything the device needs; keep only the host tables
@@ -578,7 +602,7 @@ cweno_status adopt(cweno_server* s, cweno_mesh* raw, int64_t* mesh_id) {
   for (int t = 0; t < 2; ++t)
     for (int vb = 0; vb < 10; ++vb) m->variant[t][vb] = vb == 0 ? -1 : cweno_abi::default_variant(m, vb, t == 1);
   if (hipEventCreateWithFlags(&sm->ready, hipEventDisableTiming) != hipSuccess) {
-    (void)hipHostFree(sm->image);
+    free_image(*sm);
     return fail(CWENO_E_HIP, "event creation failed");
   }
   std::lock_guard<std::mutex> g(s->mu);
@@ -705,6 +729,14 @@ cweno_status cweno_server_cancel(cweno_server* s, int64_t ticket) {
   s->queue.erase(std::find(s->queue.begin(), s->queue.end(), ticket));
   it->second.state = kCancelled;
   s->cv_done.notify_all();
+  return CWENO_OK;
+}
+
+cweno_status cweno_server_set_pinned_limit(cweno_server* s, int64_t bytes) {
+  if (!s) return fail(CWENO_E_ARG, "server is NULL");
+  if (bytes < 0) return fail(CWENO_E_ARG, "the pinned limit must not be negative");
+  std::lock_guard<std::mutex> g(s->mu);
+  s->pin_limit = (size_t)bytes;
   return CWENO_OK;
 }
 

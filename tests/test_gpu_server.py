@@ -126,7 +126,9 @@ def test_served_results_match_the_oracle_with_evictions(dtype):
             assert err <= tol, (k, err)
 
 
-def test_server_evicts_under_a_small_budget():
+@pytest.mark.parametrize("pinned", [True, False])
+def test_server_evicts_under_a_small_budget(pinned):
+    """pinned=False: a pinned limit of 0, so every image is pageable."""
     torch = torch_cuda()
     import paper_1612_09335_amd as C
     tdt, raw, direct = _setup(torch, C, "f32")
@@ -136,6 +138,8 @@ def test_server_evicts_under_a_small_budget():
     del probe
     budget = max(int(sum(sizes) * 0.5), int(max(sizes) * 1.05))
     srv = C.Server(budget, dtype="f32", max_inflight=3, n_streams=2)
+    if not pinned:
+        srv.set_pinned_limit(0)
     ids = _register_all(srv, raw)
     rng = np.random.default_rng(8)
     order = [int(k) for k in rng.integers(0, len(ids), 60)]
