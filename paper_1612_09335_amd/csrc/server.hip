@@ -499,11 +499,21 @@ cweno_status build_image(cweno_server* srv, SMesh& sm) {
   // pageable memory beyond it: the images of a large registered set can
   // exceed what the host may pin, and the runtime's own copies of pageable
   // memory need pinned staging memory that must stay available
-  sm.pinned = srv->pinned_bytes + L.total <= srv->pin_limit &&
-              hipHostMalloc(&sm.image, L.total, hipHostMallocDefault) == hipSuccess;
-  if (sm.pinned) {
-    srv->pinned_bytes += L.total;
-  } else {
+  bool reserved = false;
+  {
+    // registrations may run concurrently: reserve the pinned bytes first
+    std::lock_guard<std::mutex> g(srv->mu);
+    if (srv->pinned_bytes + L.total <= srv->pin_limit) {
+      srv->pinned_bytes += L.total;
+      reserved = true;
+    }
+  }
+  sm.pinned = reserved && hipHostMalloc(&sm.image, L.total, hipHostMallocDefault) == hipSuccess;
+  if (!sm.pinned) {
+    if (reserved) {
+      std::lock_guard<std::mutex> g(srv->mu);
+      srv->pinned_bytes -= L.total;
+    }
     (void)hipGetLastError();
     sm.image = std::malloc(L.total);
     if (!sm.image) return fail(CWENO_E_NOMEM, "host allocation of the mesh image failed");
@@ -586,6 +596,11 @@ cweno_status adopt(cweno_server* s, cweno_mesh* raw, int64_t* mesh_id) {
   sm->m.reset(raw);
   cweno_mesh* m = raw;
   if (cweno_status st = build_image(s, *sm)) {
+    if (sm->image && sm->pinned) {
+      // give back the pinned reservation of the failed registration
+      std::lock_guard<std::mutex> g(s->mu);
+      s->pinned_bytes -= sm->lay.total;
+    }
     free_image(*sm);
     return st;
   }
