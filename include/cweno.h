@@ -226,7 +226,7 @@ cweno_status cweno_reconstruct(const cweno_mesh* mesh, int n_vars, cweno_dtype d
  *
  *  mesh      created with CWENO_FLAG_MOVING (any ops, CWENO_OPS_NONE keeps
  *            no stored operators at all); its central stencil may hold at
- *            most 129 cells
+ *            most 129 cells; the work mapping is cweno_mesh_moving_shape's
  *  vertices  device, [n_vertices][dim] doubles: this call's positions
  *  n_vars, dtype, q, coeffs, sigma, omega
  *            as for cweno_reconstruct (FP32 averages and coefficients are
@@ -245,6 +245,26 @@ cweno_status cweno_reconstruct(const cweno_mesh* mesh, int n_vars, cweno_dtype d
 cweno_status cweno_reconstruct_moving(const cweno_mesh* mesh, const double* vertices, int n_vars,
                                       cweno_dtype dtype, const void* q, void* coeffs, void* sigma,
                                       void* omega, int* fault, void* hip_stream);
+
+/*
+ * cweno_mesh_set_moving_shape / cweno_mesh_moving_shape -- the work mapping
+ * of cweno_reconstruct_moving (no effect on its results beyond rounding).
+ * A segment of seg lanes (8, 16, 32 or 64) reconstructs one cell, each lane
+ * holding rpl rows (1..4) of the cell's least-squares matrix; narrower
+ * segments need fewer exchange stages per sum over the rows and serve more
+ * cells per wave.  By default the narrowest instantiated shape whose seg * rpl
+ * row slots hold the central stencil (besides the cell) is used.
+ *
+ *  set:  seg = rpl = 0 restores the default; otherwise the shape must be
+ *        instantiated for the mesh's (dim, degree) and hold its stencil.
+ *        Not while another call uses the mesh.
+ *  get:  seg, rpl (host ints) receive the shape the next call uses.
+ *
+ * Errors: CWENO_E_ARG (NULL pointers, a mesh without CWENO_FLAG_MOVING, a
+ * shape that is not instantiated or too small for the stencil).
+ */
+cweno_status cweno_mesh_set_moving_shape(cweno_mesh* mesh, int seg, int rpl);
+cweno_status cweno_mesh_moving_shape(const cweno_mesh* mesh, int* seg, int* rpl);
 
 /*
  * Point values of the reconstruction (the predictor and the fluxes use the

@@ -26,7 +26,8 @@ STATUS = {0: "CWENO_OK", -1: "CWENO_E_ARG", -2: "CWENO_E_MESH", -3: "CWENO_E_STE
           -8: "CWENO_E_HIP", -9: "CWENO_E_BUSY", -10: "CWENO_E_CANCELLED"}
 
 SYMBOLS = ("cweno_mesh_create", "cweno_mesh_destroy", "cweno_mesh_info", "cweno_mesh_tables",
-           "cweno_mesh_operators", "cweno_mesh_weno_tables", "cweno_reconstruct", "cweno_reconstruct_moving", "cweno_points_create",
+           "cweno_mesh_operators", "cweno_mesh_weno_tables", "cweno_reconstruct", "cweno_reconstruct_moving",
+           "cweno_mesh_set_moving_shape", "cweno_mesh_moving_shape", "cweno_points_create",
            "cweno_points_basis", "cweno_points_destroy", "cweno_evaluate", "cweno_reconstruct_points",
            "cweno_status_string",
            "cweno_last_error",
@@ -73,6 +74,8 @@ def _load():
     lib.cweno_mesh_operators.argtypes = [vp, i64, vp, vp, vp]
     lib.cweno_reconstruct.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
     lib.cweno_reconstruct_moving.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp]
+    lib.cweno_mesh_set_moving_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    lib.cweno_mesh_moving_shape.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.cweno_mesh_weno_tables.argtypes = [vp, ctypes.POINTER(ctypes.c_int), vp]
     lib.cweno_points_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(vp)]
     lib.cweno_points_basis.argtypes = [vp, vp]
@@ -280,6 +283,17 @@ class Mesh:
                                             None if omega is None else omega.data_ptr(),
                                             None if fault is None else fault.data_ptr(), _stream_ptr(stream)))
         return out
+
+    def set_moving_shape(self, seg, rpl):
+        """cweno_mesh_set_moving_shape: the moving kernel's work mapping (seg lanes per
+        cell, rpl stencil rows per lane); (0, 0) restores the default."""
+        _check(lib.cweno_mesh_set_moving_shape(self._h, int(seg), int(rpl)))
+
+    def moving_shape(self):
+        """cweno_mesh_moving_shape: (seg, rpl) of the next moving-mesh call."""
+        seg, rpl = ctypes.c_int(), ctypes.c_int()
+        _check(lib.cweno_mesh_moving_shape(self._h, ctypes.byref(seg), ctypes.byref(rpl)))
+        return seg.value, rpl.value
 
     def evaluate(self, points, coeffs, out=None, stream=None):
         """cweno_evaluate: coeffs [n_vars, n_basis, n_cells] -> values [n_vars, n_points, n_cells]."""

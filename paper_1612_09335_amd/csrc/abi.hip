@@ -88,7 +88,7 @@ cweno_status alloc_zero(DevBuf& b, size_t bytes, hipStream_t s, int64_t& total) 
 }
 
 // Per-cell operators built on the device from the host's stencils: the
-// vertices, cells, stencils and quadrature rule go up (kept for a moving mesh,
+// vertices, cells and stencils go up (kept for a moving mesh,
 // freed otherwise), the assembly kernel writes pinv/binv/mask in the stored
 // layout, and its fault word turns into an error.
 cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int32_t* cells, int ops, hipStream_t s) {
@@ -96,15 +96,8 @@ cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int
   int seg = 0, rpl = 0;
   if (!cweno::move_shape(dim, m->M, m->n_e - 1, seg, rpl, true))
     return fail(CWENO_E_ARG, "device operator assembly supports central stencils of at most 65 cells");
-  std::vector<double> lam, w, rule;
-  cweno::grundmann_moller(dim, m->M, lam, w);
-  const int nq = (int)w.size();
-  for (int k = 0; k < nq; ++k) {
-    for (int v = 0; v <= dim; ++v) rule.push_back(lam[(size_t)k * (dim + 1) + v]);
-    rule.push_back(w[k]);
-  }
   int64_t scratch_bytes = 0;
-  DevBuf V, C, S0, SS, SP, R, F;
+  DevBuf V, C, S0, SS, SP, F;
   const std::vector<uint8_t> sp = cweno_abi::sector_rows(dim, m->nc, m->n_e, m->central, m->sectors);
   const bool keep = (m->flags & CWENO_FLAG_MOVING) != 0;
   cweno_status st;
@@ -113,7 +106,7 @@ cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int
     for (DevBuf* b : {&V, &F})
       if (b->p) (void)hipFree(b->p);
     if (tables)
-      for (DevBuf* b : {&C, &S0, &SS, &SP, &R})
+      for (DevBuf* b : {&C, &S0, &SS, &SP})
         if (b->p) (void)hipFree(b->p);
   };
   int64_t& tot = keep ? m->device_bytes : scratch_bytes;
@@ -121,8 +114,7 @@ cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int
       (st = upload(C, cells, (size_t)m->nc * (dim + 1) * 4, s, tot)) ||
       (st = upload(S0, m->central.data(), m->central.size() * 4, s, tot)) ||
       (st = upload(SS, m->sectors.data(), m->sectors.size() * 4, s, tot)) ||
-      (st = upload(SP, sp.data(), sp.size(), s, tot)) ||
-      (st = upload(R, rule.data(), rule.size() * 8, s, tot)) || (st = alloc_zero(F, 4, s, scratch_bytes))) {
+      (st = upload(SP, sp.data(), sp.size(), s, tot)) || (st = alloc_zero(F, 4, s, scratch_bytes))) {
     release(true);
     return st;
   }
@@ -143,7 +135,6 @@ cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int
   p.S0 = (const int32_t*)S0.p;
   p.SS = (const int32_t*)SS.p;
   p.SP = (const uint8_t*)SP.p;
-  p.rule = (const double*)R.p;
   p.fault = (int*)F.p;
   p.pinv64 = (double*)m->pinv64.p;
   p.pinv32 = (float*)m->pinv32.p;
@@ -159,7 +150,6 @@ cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int
   p.eps = m->eps;
   p.nc = m->nc;
   p.n_e = m->n_e;
-  p.nq = nq;
   p.r = m->r;
   hipError_t e = cweno::launch_assemble(dim, m->M, p, seg, s);
   int fault = 0;
@@ -172,8 +162,6 @@ cweno_status assemble_on_device(cweno_mesh* m, const double* vertices, const int
     m->mvS0 = S0;
     m->mvSS = SS;
     m->mvSP = SP;
-    m->mvRule = R;
-    m->nq = nq;
   }
   release(!keep);
   if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("operator assembly failed: ") + hipGetErrorString(e));
@@ -438,20 +426,12 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
         return fail(CWENO_E_NOMEM, "host allocation failed during device assembly");
       }
     } else if (o.flags & CWENO_FLAG_MOVING) {
-      // connectivity, stencils and the quadrature rule for the moving-mesh kernel
-      std::vector<double> lam, w, rule;
-      cweno::grundmann_moller(dim, degree, lam, w);
-      m->nq = (int)w.size();
-      for (int k = 0; k < m->nq; ++k) {
-        for (int v = 0; v <= dim; ++v) rule.push_back(lam[(size_t)k * (dim + 1) + v]);
-        rule.push_back(w[k]);
-      }
+      // connectivity and stencils for the moving-mesh kernel
       if ((st = upload(m->mvC, cells, (size_t)n_cells * (dim + 1) * 4, s, m->device_bytes))) return st;
       if ((st = upload(m->mvS0, m->central.data(), m->central.size() * 4, s, m->device_bytes))) return st;
       if ((st = upload(m->mvSS, m->sectors.data(), m->sectors.size() * 4, s, m->device_bytes))) return st;
       const std::vector<uint8_t> sp = cweno_abi::sector_rows(dim, n_cells, m->n_e, m->central, m->sectors);
       if ((st = upload(m->mvSP, sp.data(), sp.size(), s, m->device_bytes))) return st;
-      if ((st = upload(m->mvRule, rule.data(), rule.size() * 8, s, m->device_bytes))) return st;
     }
     if (o.ops == CWENO_OPS_F64 || o.ops == CWENO_OPS_BOTH) {
       if (!dev_ops) {

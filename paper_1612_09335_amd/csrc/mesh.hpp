@@ -74,9 +74,9 @@ struct cweno_mesh {
   cweno_abi::DevBuf pinv64, binv64, sigma64, pinv32, binv32, sigma32, gidx, secpos, mask, halo, hoff, lidx;
   int maxH = 0;
   // moving meshes: cell vertex ids, central and sector stencils (cell-major),
-  // quadrature rule [nq][d+2]
-  cweno_abi::DevBuf mvC, mvS0, mvSS, mvSP, mvRule;
-  int nq = 0;
+  // each sector cell's row in the central stencil
+  cweno_abi::DevBuf mvC, mvS0, mvSS, mvSP;
+  int mv_seg = 0, mv_rpl = 0;   // work mapping set by the caller; 0 = the default shape
   int64_t n_vertices = 0;
   // classical WENO meshes (n_s > 0): stencil tables [nc][n_s][n_e] on the host;
   // operators, kept-stencil bits and the halos of blocks of 64 cells (cells,
@@ -94,7 +94,7 @@ struct cweno_mesh {
   ~cweno_mesh() {
     if (!owns_device) return;
     for (cweno_abi::DevBuf* b : {&pinv64, &binv64, &sigma64, &pinv32, &binv32, &sigma32, &gidx, &secpos, &mask, &halo,
-                                 &hoff, &lidx, &mvC, &mvS0, &mvSS, &mvSP, &mvRule, &wpinv, &walive, &whalo, &whoff, &wlidx})
+                                 &hoff, &lidx, &mvC, &mvS0, &mvSS, &mvSP, &wpinv, &walive, &whalo, &whoff, &wlidx})
       if (b->p) (void)hipFree(b->p);
   }
 };

@@ -10,17 +10,20 @@ namespace cweno {
 
 // Segment shapes (lanes per cell, rows per lane) instantiated for (D, M): the
 // rows of R must lie in the segment's row slots (fewer basis functions than
-// lanes times rows per lane), four rows per lane only on 16 lanes, and two
-// rows per lane on 64 lanes only for the wide 3-D stencils.
+// lanes times rows per lane), three rows per lane only on 8 lanes, four only
+// on 8 or 16, and two rows per lane on 64 lanes only for the wide 3-D
+// stencils.
 __host__ __device__ constexpr bool move_shape_ok(int D, int M, int seg, int rpl) {
-  return (seg == 16 || seg == 32 || seg == 64) && (rpl == 1 || rpl == 2 || rpl == 4) &&
-         nbasis_c(M, D) - 1 < seg * rpl && (rpl < 4 || seg == 16) && (seg < 64 || rpl == 1 || (D == 3 && M >= 2));
+  return (seg == 8 || seg == 16 || seg == 32 || seg == 64) && rpl >= 1 && rpl <= 4 &&
+         nbasis_c(M, D) - 1 < seg * rpl && (rpl != 3 || seg == 8) && (rpl < 4 || seg <= 16) &&
+         (seg < 64 || rpl == 1 || (D == 3 && M >= 2));
 }
 
 // Preferred shapes, in order: the narrowest segment whose rows hold the
 // stencil, with as few rows per lane as that allows (fewer exchange stages per
 // sum, more cells per wave instruction).
-constexpr int kMoveShapes[7][2] = {{16, 1}, {16, 2}, {16, 4}, {32, 1}, {32, 2}, {64, 1}, {64, 2}};
+constexpr int kMoveShapes[11][2] = {{8, 1},  {8, 2},  {8, 3},  {8, 4},  {16, 1}, {16, 2},
+                                    {16, 4}, {32, 1}, {32, 2}, {64, 1}, {64, 2}};
 
 // First instantiated shape whose rows hold the NE1 stencil cells besides the
 // cell (with one_row, among the shapes of one row per lane); false if none
@@ -51,7 +54,7 @@ CWENO_DECL_ASM(2, 1) CWENO_DECL_ASM(2, 2) CWENO_DECL_ASM(2, 3) CWENO_DECL_ASM(2,
 CWENO_DECL_ASM(3, 1) CWENO_DECL_ASM(3, 2) CWENO_DECL_ASM(3, 3) CWENO_DECL_ASM(3, 4)
 #undef CWENO_DECL_ASM
 
-// Operator assembly on the device: p's V, C, S0, SS and rule describe the mesh,
+// Operator assembly on the device: p's V, C, S0, SS and SP describe the mesh,
 // its pinv/binv/mask pointers receive the operators (one row per lane, so the
 // central stencil may hold at most 65 cells).
 inline hipError_t launch_assemble(int d, int m, const MParams<double>& p, int seg, hipStream_t s) {

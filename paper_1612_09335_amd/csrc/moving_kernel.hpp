@@ -5,7 +5,7 @@
 // at every step (Sec. 2.1), so storing them buys nothing; this trades the
 // operator stream for arithmetic.
 //
-// Work mapping.  A segment of SEG lanes (16, 32 or 64) owns one cell.  Lane t
+// Work mapping.  A segment of SEG lanes (8, 16, 32 or 64) owns one cell.  Lane t
 // of the segment owns rows t, t + SEG, ... (RPL rows) of the cell's least-
 // squares matrix A' (row k: stencil cell k+1).  Per cell:
 //   1. every lane unwraps the cell's vertices (minimum image around vertex 0)
@@ -47,10 +47,13 @@
 namespace cweno {
 
 // Variables reflected together (a pass): 2, 5 or 9; at most 5 where the
-// basis has more than 15 functions (the register budget of the 3-D M >= 3 rows).
-__host__ __device__ constexpr int move_vb_max(int D, int M) { return nbasis_c(M, D) - 1 <= 14 ? 9 : 5; }
-__host__ __device__ constexpr int move_vb(int D, int M, int nv) {
-  return nv <= 2 ? 2 : (nv <= 5 || move_vb_max(D, M) == 5) ? 5 : 9;
+// basis has more than 15 functions (the register budget of the 3-D M >= 3
+// rows) and on 8-lane segments (one lane per variable forms the blend).
+__host__ __device__ constexpr int move_vb_max(int D, int M, int SEG) {
+  return nbasis_c(M, D) - 1 <= 14 && SEG >= 9 ? 9 : 5;
+}
+__host__ __device__ constexpr int move_vb(int D, int M, int SEG, int nv) {
+  return nv <= 2 ? 2 : (nv <= 5 || move_vb_max(D, M, SEG) == 5) ? 5 : 9;
 }
 constexpr int kMoveThreads = 256;  // four waves per block
 
@@ -74,7 +77,6 @@ struct MParams {
   const int32_t* S0;      // [nc][n_e] central stencil, the cell first
   const int32_t* SS;      // [nc][D+1][D+1] sector stencils, the cell first; first entry < 0: not filled
   const uint8_t* SP;      // [nc][D+1][D] row of each sector cell in the central stencil (its position - 1), 255: not in it
-  const double* rule;     // [nq][D+2] quadrature: barycentric coordinates, then the weight (weights sum 1)
   const T* q;             // [nv][nc]
   T* out;                 // [nv][NB][nc]
   T* sig;                 // optional [nv][D+2][nc]
@@ -93,7 +95,7 @@ struct MParams {
   double lam[5];          // linear weights lambda_0 .. lambda_{D+1}
   double eps;
   int64_t nc;
-  int n_e, nq, nv, r, sigma0_popt, linear_w;
+  int n_e, nv, r, sigma0_popt, linear_w;
 };
 
 // f(std::integral_constant<int, I>) for I = 0 .. N-1, each call with a
@@ -128,6 +130,13 @@ __device__ __forceinline__ double dpp_d(double x) {
   return mkd((uint32_t)__builtin_amdgcn_mov_dpp((int)lo32(x), CTRL, 0xF, 0xF, false),
              (uint32_t)__builtin_amdgcn_mov_dpp((int)hi32(x), CTRL, 0xF, 0xF, false));
 }
+// As dpp_d, written only to the lanes of the banks (groups of 4 lanes within
+// each row) set in BANKS; the other lanes keep old.
+template <int CTRL, int BANKS>
+__device__ __forceinline__ double dpp_upd_d(double old, double x) {
+  return mkd((uint32_t)__builtin_amdgcn_update_dpp((int)lo32(old), (int)lo32(x), CTRL, 0xF, BANKS, false),
+             (uint32_t)__builtin_amdgcn_update_dpp((int)hi32(old), (int)hi32(x), CTRL, 0xF, BANKS, false));
+}
 // Swizzle (bit-mask mode) of a double within each group of 32 lanes.
 template <int PAT>
 __device__ __forceinline__ double swz_d(double x) {
@@ -145,6 +154,8 @@ constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141; // lane 7-l within each 8
 constexpr int kDppMirror = 0x140;     // lane 15-l within each 16
 constexpr int kSwzXor16 = 0x401F;     // and 0x1f, xor 0x10
+constexpr int kDppRowShl4 = 0x104;    // lane l + 4 within each 16
+constexpr int kDppRowShr4 = 0x114;    // lane l - 4 within each 16
 
 // x[c] for first <= c < last := the sum of x[c] over the lanes of the segment,
 // the same bits in every lane (each stage pairs every lane with one lane of
@@ -152,7 +163,7 @@ constexpr int kSwzXor16 = 0x401F;     // and 0x1f, xor 0x10
 // of the wave must be active.
 template <int SEG, int N>
 __device__ __forceinline__ void seg_sum(double (&x)[N], int first = 0, int last = N) {
-  static_assert(SEG == 16 || SEG == 32 || SEG == 64, "segment of 16, 32 or 64 lanes");
+  static_assert(SEG == 8 || SEG == 16 || SEG == 32 || SEG == 64, "segment of 8, 16, 32 or 64 lanes");
 #pragma unroll
   for (int c = 0; c < N; ++c)
     if (c >= first && c < last) x[c] += dpp_d<kDppXor1>(x[c]);
@@ -162,9 +173,11 @@ __device__ __forceinline__ void seg_sum(double (&x)[N], int first = 0, int last 
 #pragma unroll
   for (int c = 0; c < N; ++c)
     if (c >= first && c < last) x[c] += dpp_d<kDppHalfMirror>(x[c]);
+  if constexpr (SEG >= 16) {
 #pragma unroll
-  for (int c = 0; c < N; ++c)
-    if (c >= first && c < last) x[c] += dpp_d<kDppMirror>(x[c]);
+    for (int c = 0; c < N; ++c)
+      if (c >= first && c < last) x[c] += dpp_d<kDppMirror>(x[c]);
+  }
   if constexpr (SEG >= 32) {
 #pragma unroll
     for (int c = 0; c < N; ++c)
@@ -178,11 +191,18 @@ __device__ __forceinline__ void seg_sum(double (&x)[N], int first = 0, int last 
 }
 
 // Value of x in lane SRC of this lane's segment.  A 16-lane segment is one
-// DPP row: the row's lane SRC is broadcast to the row (row_newbcast).
+// DPP row: the row's lane SRC is broadcast to the row (row_newbcast).  An
+// 8-lane segment is half a row: lane SRC % 4 of every quad goes to its quad
+// (quad_perm), then the quad that holds lane SRC of the segment goes to the
+// segment's other quad (a row shift by 4 written to that quad's banks only).
 template <int SEG, int SRC>
 __device__ __forceinline__ double seg_bcast(double x, int seg) {
   static_assert(SRC >= 0 && SRC < SEG, "lane of the segment");
-  if constexpr (SEG == 16) {
+  if constexpr (SEG == 8) {
+    const double a = dpp_d<(SRC % 4) * 0x55>(x);
+    if constexpr (SRC < 4) return dpp_upd_d<kDppRowShr4, 0xA>(a, a);
+    else return dpp_upd_d<kDppRowShl4, 0x5>(a, a);
+  } else if constexpr (SEG == 16) {
     return dpp_d<0x150 + SRC>(x);
   } else if constexpr (SEG == 64) {
     return rdl_d(x, SRC);
@@ -193,6 +213,24 @@ __device__ __forceinline__ double seg_bcast(double x, int seg) {
 }
 
 // ---------------------------------------------------------------- small dense algebra
+
+// 1/x for finite non-zero x whose reciprocal is a normal number (either sign):
+// the refined hardware estimate, within an ulp or two of the quotient.
+__device__ __forceinline__ double rcp_nz(double x) { return rcp_pos(x); }
+
+// sqrt(x) for finite x >= 0 (0 for 0), within about an ulp: the hardware
+// estimate y of 1/sqrt(x), one Goldschmidt step on g = x y, h = y / 2
+// (r = 1/2 - g h; g += g r; h += h r), then two corrections g += (x - g^2) h.
+__device__ __forceinline__ double sqrt_nn(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  g = fma(fma(-g, g, x), h, g);
+  g = fma(fma(-g, g, x), h, g);
+  return x > 0.0 ? g : 0.0;
+}
 
 // Minimum image of a difference d along an axis of period L (iL = 1/L; L = 0:
 // not periodic).  The product by the reciprocal decides the same image as a
@@ -227,7 +265,7 @@ __device__ __forceinline__ bool invert_small(const double (&A)[N][N], double (&A
     }
     const double pv = W[c][c];
     ok = ok && pv != 0.0;
-    const double ip = 1.0 / pv;
+    const double ip = rcp_nz(pv);   // meaningless where pv = 0 (ok is then false)
 #pragma unroll
     for (int k = 0; k < 2 * N; ++k) W[c][k] *= ip;
 #pragma unroll
@@ -310,9 +348,19 @@ __host__ __device__ constexpr int basis_index(int D, int p, int q, int r) {
   return l + (n - p - q);
 }
 
-// acc[l - 1] += w * psi_l(xi) for l = 1 .. NB-1: the orthonormal collapsed-
-// coordinate (Dubiner) basis, (1/|T_E|) int psi^2 = 1, evaluated factor by
-// factor so that no table of all values is held.
+// Normalisation of psi_{p,q,r} (r = 0 in 2-D): the constant that makes the
+// collapsed-coordinate product of Jacobi polynomials orthonormal,
+// (1/|T_E|) int psi^2 = 1.
+template <int D>
+__device__ __forceinline__ double basis_norm(int p, int q, int r) {
+  return D == 2 ? __builtin_sqrt((2.0 * p + 1.0) * (p + q + 1.0))
+                : __builtin_sqrt((2.0 * p + 1.0) * (2.0 * p + 2.0 * q + 2.0) * (2.0 * p + 2.0 * q + 2.0 * r + 3.0) / 6.0);
+}
+
+// acc[l - 1] += w * psi_l(xi) / n_l for l = 1 .. NB-1, n_l the normalisation
+// of psi_l (applied once to the sums by basis_normalise): the orthonormal
+// collapsed-coordinate (Dubiner) basis evaluated factor by factor, so that no
+// table of all values is held.
 template <int D, int M>
 __device__ __forceinline__ void basis_accumulate(const double (&xi)[D], double w, double (&acc)[nbasis_c(M, D) - 1]) {
   if constexpr (D == 2) {
@@ -327,9 +375,8 @@ __device__ __forceinline__ void basis_accumulate(const double (&xi)[D], double w
 #pragma unroll
       for (int q = 0; q <= M; ++q) {
         if (p + q == 0 || p + q > M) continue;
-        const double nrm = __builtin_sqrt((2.0 * p + 1.0) * (p + q + 1.0));
         const int l = basis_index(2, p, q, 0);
-        acc[l - 1] = fma(wf * nrm, G[q], acc[l - 1]);
+        acc[l - 1] = fma(wf, G[q], acc[l - 1]);
       }
     }
   } else {
@@ -349,14 +396,26 @@ __device__ __forceinline__ void basis_accumulate(const double (&xi)[D], double w
 #pragma unroll
         for (int r = 0; r <= M; ++r) {
           if (p + q + r == 0 || p + q + r > M) continue;
-          const double nrm = __builtin_sqrt((2.0 * p + 1.0) * (2.0 * p + 2.0 * q + 2.0) *
-                                            (2.0 * p + 2.0 * q + 2.0 * r + 3.0) / 6.0);
           const int l = basis_index(3, p, q, r);
-          acc[l - 1] = fma(wfh * nrm, K[r], acc[l - 1]);
+          acc[l - 1] = fma(wfh, K[r], acc[l - 1]);
         }
       }
     }
   }
+}
+
+// acc[l - 1] *= n_l: the sums of basis_accumulate made sums of psi_l.
+template <int D, int M>
+__device__ __forceinline__ void basis_normalise(double (&acc)[nbasis_c(M, D) - 1]) {
+#pragma unroll
+  for (int p = 0; p <= M; ++p)
+#pragma unroll
+    for (int q = 0; q <= M; ++q)
+#pragma unroll
+      for (int r = 0; r <= (D == 3 ? M : 0); ++r) {
+        if (p + q + r == 0 || p + q + r > M) continue;
+        acc[basis_index(D, p, q, r) - 1] *= basis_norm<D>(p, q, r);
+      }
 }
 
 // The d linear basis functions psi_1 .. psi_d at xi.
@@ -366,9 +425,71 @@ __device__ __forceinline__ void linear_basis(const double (&xi)[D], double (&out
 #pragma unroll
   for (int l = 0; l < D; ++l) acc[l] = 0.0;
   basis_accumulate<D, 1>(xi, 1.0, acc);
+  basis_normalise<D, 1>(acc);
 #pragma unroll
   for (int l = 0; l < D; ++l) out[l] = acc[l];
 }
+
+// ---------------------------------------------------------------- quadrature
+
+// The Grundmann-Moller rule on the D-simplex of degree 2s + 1, s = M / 2 (the
+// smallest odd degree >= M), for averages: for i = 0 .. s and every
+// beta in N^(D+1) with |beta| = s - i, the point with barycentric
+// coordinates (2 beta_k + 1) / g, g = D + 2s + 1 - 2i, and weight
+// D! (-1)^i 2^(-2s) g^(2s+1) / (i! (D + 2s + 1 - i)!) (Grundmann and Moller,
+// SIAM J. Numer. Anal. 15, 1978; the weights sum to 1).  Built at compile
+// time, so that the points and weights are immediates of the unrolled code.
+__host__ __device__ constexpr int gm_points_c(int D, int M) {
+  int n = 0;
+  for (int i = 0; i <= M / 2; ++i) {
+    const int m = M / 2 - i;   // compositions of m into D + 1 parts: C(m + D, D)
+    int c = 1;
+    for (int k = 1; k <= D; ++k) c = c * (m + k) / k;
+    n += c;
+  }
+  return n;
+}
+
+template <int D, int M>
+struct GMRule {
+  static constexpr int NQ = gm_points_c(D, M);
+  double lam[NQ][D + 1];
+  double w[NQ];
+  constexpr GMRule() : lam{}, w{} {
+    const int s = M / 2;
+    double fd = 1.0;
+    for (int k = 2; k <= D; ++k) fd *= k;
+    int q = 0;
+    for (int i = 0; i <= s; ++i) {
+      const int g = D + 2 * s + 1 - 2 * i, m = s - i;
+      double c = (i % 2) ? -fd : fd;
+      for (int k = 0; k < 2 * s; ++k) c *= 0.5;
+      for (int k = 0; k < 2 * s + 1; ++k) c *= g;
+      for (int k = 2; k <= i; ++k) c /= k;
+      for (int k = 2; k <= D + 2 * s + 1 - i; ++k) c /= k;
+      // every beta in [0, m]^(D+1) with |beta| = m, as the digits of t in base m + 1
+      int span = 1;
+      for (int k = 0; k <= D; ++k) span *= m + 1;
+      for (int t = 0; t < span; ++t) {
+        int b[D + 1] = {}, sum = 0, x = t;
+        for (int k = 0; k <= D; ++k) {
+          b[k] = x % (m + 1);
+          x /= m + 1;
+          sum += b[k];
+        }
+        if (sum != m) continue;
+        for (int k = 0; k <= D; ++k) lam[q][k] = (2.0 * b[k] + 1.0) / g;
+        w[q] = c;
+        ++q;
+      }
+    }
+  }
+};
+
+template <int D, int M>
+struct GMTable {
+  static constexpr GMRule<D, M> v{};
+};
 
 // ---------------------------------------------------------------- geometry
 
@@ -395,7 +516,7 @@ __device__ __forceinline__ void barycentre(const double (&X)[D + 1][D], double (
     double s = X[0][a];
 #pragma unroll
     for (int v = 1; v <= D; ++v) s = s + X[v][a];
-    c[a] = s / (double)(D + 1);
+    c[a] = s * (1.0 / (D + 1));
   }
 }
 
@@ -411,6 +532,7 @@ void moving_kernel(MParams<T> p) {
   constexpr int CPB = (kMoveThreads / 64) * CPW;         // cells per block
   constexpr int CH = 8;                                  // column sums in flight
   static_assert(NL < SEG * RPL, "the rows of R lie in the segment's row slots");
+  static_assert(VB <= SEG && NS <= SEG, "one lane per variable and per sector");
   // per-cell LDS record (doubles): P_opt of a pass of variables (or, when
   // assembling operators, the rows of R), column scales, diagonal of R,
   // reflector factors, sector inverses, each row cell's barycentre in the
@@ -496,17 +618,19 @@ void moving_kernel(MParams<T> p) {
           Y[v][r] = s;
         }
       }
-      for (int qq = 0; qq < p.nq; ++qq) {
-        const double* w = p.rule + qq * (D + 2);
+      using GM = GMTable<D, M>;
+#pragma unroll
+      for (int qq = 0; qq < GMRule<D, M>::NQ; ++qq) {
         double xi[D];
 #pragma unroll
         for (int r = 0; r < D; ++r) xi[r] = 0.0;
 #pragma unroll
         for (int v = 0; v < NS; ++v)
 #pragma unroll
-          for (int r = 0; r < D; ++r) xi[r] = fma(w[v], Y[v][r], xi[r]);
-        basis_accumulate<D, M>(xi, w[D + 1], a);
+          for (int r = 0; r < D; ++r) xi[r] = fma(GM::v.lam[qq][v], Y[v][r], xi[r]);
+        basis_accumulate<D, M>(xi, GM::v.w[qq], a);
       }
+      basis_normalise<D, M>(a);
     }
 #pragma unroll
     for (int l = 0; l < NL; ++l) A[t][l] = a[l];
@@ -526,12 +650,12 @@ void moving_kernel(MParams<T> p) {
     seg_sum<SEG, NL>(cn, 0);
 #pragma unroll
     for (int c = 0; c < NL; ++c) {
-      const double s = sqrt(cn[c]);
-      if (!(s > 0.0)) fault |= 2;
-      const double is = 1.0 / s;
+      const double s = sqrt_nn(cn[c]);
+      fault |= s > 0.0 ? 0 : 2;
+      const double is = rcp_pos(s);
 #pragma unroll
       for (int t = 0; t < RPL; ++t) A[t][c] *= is;
-      if (sl == 0) L[OSC + c] = s;
+      L[OSC + c] = s;   // every lane of the segment holds the same bits
     }
   }
   // 3b. Householder QR; reflector k replaces column k from row k down (the
@@ -547,12 +671,12 @@ void moving_kernel(MParams<T> p) {
       nn[0] = fma(x[t], x[t], nn[0]);
     }
     seg_sum<SEG, 1>(nn, 0);
-    const double nrm = sqrt(nn[0]);
+    const double nrm = sqrt_nn(nn[0]);
     const double akk = seg_bcast<SEG, k % SEG>(A[k / SEG][k], seg);
     const double alpha = akk > 0.0 ? -nrm : nrm;
     const double vn2 = 2.0 * nrm * (nrm + fabs(akk));   // |x - alpha e_k|^2
-    if (!(vn2 > 0.0)) fault |= 2;
-    const double tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+    fault |= vn2 > 0.0 ? 0 : 2;
+    const double tau = vn2 > 0.0 ? 2.0 * rcp_pos(vn2) : 0.0;
     double vk[RPL];
 #pragma unroll
     for (int t = 0; t < RPL; ++t) vk[t] = row[t] == k ? akk - alpha : x[t];
@@ -587,10 +711,10 @@ void moving_kernel(MParams<T> p) {
 #pragma unroll
     for (int t = 0; t < RPL; ++t)
       if (row[t] >= k) A[t][k] = vk[t];
-    if (sl == 0) {
-      L[ORD + k] = alpha;
-      L[OTAU + k] = tau;
-    }
+    // the same bits in every lane of the segment: written without a branch,
+    // so that nothing divides the steps for the scheduler
+    L[ORD + k] = alpha;
+    L[OTAU + k] = tau;
   };
   StaticFor<0, NL>::run(qr_step);
 
@@ -635,9 +759,26 @@ void moving_kernel(MParams<T> p) {
         }
         linear_basis<D>(xi, B[a]);
       }
-      // 2-norm condition number sigma_max(B) sigma_max(B^-1), kept up to 1e10
+      // 2-norm condition number k = sigma_max(B) sigma_max(B^-1), kept up to
+      // 1e10.  The Frobenius product kF = |B|_F |B^-1|_F bounds it,
+      // k <= kF <= d k, and decides unless kF lies in (1e10, d 1e10]; only
+      // there are the largest singular values computed
       double Binv[D][D];
-      if (invert_small<D>(B, Binv) && sqrt(sigma_max_sq<D>(B) * sigma_max_sq<D>(Binv)) <= 1e10) {
+      bool keep = invert_small<D>(B, Binv);
+      if (keep) {
+        double fb = 0.0, fi = 0.0;
+#pragma unroll
+        for (int l = 0; l < D; ++l)
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            fb = fma(B[l][a], B[l][a], fb);
+            fi = fma(Binv[l][a], Binv[l][a], fi);
+          }
+        const double kf2 = fb * fi;
+        keep = kf2 <= 1e20;
+        if (!keep && kf2 <= (double)(D * D) * 1e20) keep = sigma_max_sq<D>(B) * sigma_max_sq<D>(Binv) <= 1e20;
+      }
+      if (keep) {
         kept = true;
 #pragma unroll
         for (int l = 0; l < D; ++l)
@@ -665,10 +806,11 @@ void moving_kernel(MParams<T> p) {
       lam[s + 1] = ((kmask >> s) & 1u) ? p.lam[s + 1] : 0.0;
       lsum += lam[s + 1];
     }
+    const double il = rcp_pos(lsum);
 #pragma unroll
-    for (int s = 0; s <= NS; ++s) lam[s] /= lsum;
+    for (int s = 0; s <= NS; ++s) lam[s] *= il;
   }
-  const double inv_l0 = 1.0 / lam[0];
+  const double inv_l0 = rcp_pos(lam[0]);
 
   if (sl == 0) {   // rank: every diagonal entry of R above 1e-12 of the largest
     double rmax = 0.0;
@@ -788,7 +930,7 @@ void moving_kernel(MParams<T> p) {
     // the lane of row k, broadcast, and removed from the rows above it
     auto back = [&](auto kc) {
       constexpr int k = NL - 1 - decltype(kc)::value;
-      const double ik = 1.0 / L[ORD + k];
+      const double ik = rcp_nz(L[ORD + k]);
       double xk[VB];
 #pragma unroll
       for (int v = 0; v < VB; ++v) xk[v] = seg_bcast<SEG, k % SEG>(dq[k / SEG][v], seg) * ik;
@@ -805,7 +947,7 @@ void moving_kernel(MParams<T> p) {
 #pragma unroll
     for (int t = 0; t < RPL; ++t)
       if (t * SEG < NL && row[t] < NL) {
-        const double f = 1.0 / (L[ORD + row[t]] * L[OSC + row[t]]);
+        const double f = rcp_nz(L[ORD + row[t]] * L[OSC + row[t]]);
 #pragma unroll
         for (int v = 0; v < VB; ++v) L[OP + v * NL + row[t]] = dq[t][v] * f;
       }
@@ -876,7 +1018,7 @@ void moving_kernel(MParams<T> p) {
         // every kept ratio is at most 1, so its power cannot overflow; a
         // dropped sector (lambda_s = 0, sigma_s = 0) gets ratio 0, since
         // (m_min / eps)^r overflows for large r or data, and inf * 0 is NaN
-        for (int s = 0; s <= NS; ++s) om[s] = lam[s] > 0.0 ? mmin / ms[s] : 0.0;
+        for (int s = 0; s <= NS; ++s) om[s] = lam[s] > 0.0 ? mmin * rcp_pos(ms[s]) : 0.0;
         powi<NS + 1, double>(om, p.r);
         double tot = 0.0;
 #pragma unroll
@@ -884,7 +1026,7 @@ void moving_kernel(MParams<T> p) {
           om[s] *= lam[s];
           tot += om[s];
         }
-        const double itot = 1.0 / tot;
+        const double itot = rcp_pos(tot);
 #pragma unroll
         for (int s = 0; s <= NS; ++s) om[s] *= itot;
       }

@@ -29,7 +29,7 @@ namespace {
 
 template <int SEG, int RPL, int VB>
 hipError_t launch_vb(const MParams<real_t>& p, hipStream_t s) {
-  if constexpr (VB <= move_vb_max(CWENO_D, CWENO_M)) {
+  if constexpr (VB <= move_vb_max(CWENO_D, CWENO_M, SEG)) {
     constexpr int cpb = (kMoveThreads / 64) * (64 / SEG);
     const int64_t blocks = (p.nc + cpb - 1) / cpb;
     hipLaunchKernelGGL((moving_kernel<CWENO_D, CWENO_M, SEG, RPL, VB, real_t>), dim3((unsigned)blocks),
@@ -43,7 +43,7 @@ hipError_t launch_vb(const MParams<real_t>& p, hipStream_t s) {
 template <int SEG, int RPL>
 hipError_t launch_shape(const MParams<real_t>& p, hipStream_t s) {
   if constexpr (move_shape_ok(CWENO_D, CWENO_M, SEG, RPL)) {
-    switch (move_vb(CWENO_D, CWENO_M, p.nv)) {
+    switch (move_vb(CWENO_D, CWENO_M, SEG, p.nv)) {
       case 2: return launch_vb<SEG, RPL, 2>(p, s);
       case 5: return launch_vb<SEG, RPL, 5>(p, s);
       case 9: return launch_vb<SEG, RPL, 9>(p, s);
@@ -69,6 +69,7 @@ hipError_t CWENO_ASM_FN(CWENO_D, CWENO_M)(const MParams<double>& p, int seg, hip
       return hipErrorInvalidValue;
     }
   };
+  if (seg == 8) return go(std::integral_constant<int, 8>{});
   if (seg == 16) return go(std::integral_constant<int, 16>{});
   if (seg == 32) return go(std::integral_constant<int, 32>{});
   if (seg == 64) return go(std::integral_constant<int, 64>{});
@@ -77,6 +78,10 @@ hipError_t CWENO_ASM_FN(CWENO_D, CWENO_M)(const MParams<double>& p, int seg, hip
 #endif
 
 hipError_t CWENO_MOVE_FN(CWENO_TN, CWENO_D, CWENO_M)(const MParams<real_t>& p, int seg, int rpl, hipStream_t s) {
+  if (seg == 8 && rpl == 1) return launch_shape<8, 1>(p, s);
+  if (seg == 8 && rpl == 2) return launch_shape<8, 2>(p, s);
+  if (seg == 8 && rpl == 3) return launch_shape<8, 3>(p, s);
+  if (seg == 8 && rpl == 4) return launch_shape<8, 4>(p, s);
   if (seg == 16 && rpl == 1) return launch_shape<16, 1>(p, s);
   if (seg == 16 && rpl == 2) return launch_shape<16, 2>(p, s);
   if (seg == 16 && rpl == 4) return launch_shape<16, 4>(p, s);

@@ -259,3 +259,62 @@ def test_bounded_moved_mesh_dropped_sectors(case, r):
     err32 = data_scaled_error(r32["coeffs"][:, :, idx], ref32["coeffs"], Q32, st)
     print(f"[gpu moving bounded]   f32 data-scaled error {err32:.3e}", flush=True)
     assert err32 <= TOL32
+
+
+SHAPES = [(8, 1), (8, 2), (8, 3), (8, 4), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2), (64, 1), (64, 2)]
+SHAPE_CASES = {
+    # name: (mesh factory, degree, variables); nine variables on 8 lanes take two passes
+    "tri12_M3_nv9": (lambda: tri_mesh(12, 0.15, 570), 3, 9),
+    "kuhn4_M2_nv5": (lambda: kuhn_tet_mesh(4, 0.1, 571), 2, 5),
+    "kuhn5_M3_nv3": (lambda: kuhn_tet_mesh(5, 0.1, 572), 3, 3),
+}
+
+
+@pytest.mark.parametrize("case", list(SHAPE_CASES))
+def test_every_segment_shape_against_oracle(case):
+    """Every work mapping the library instantiates for (dim, degree) and that
+    holds the stencil gives the oracle's reconstruction (FP64 bar; FP32 bar
+    for FP32 averages); shapes that are not instantiated or too small are
+    refused, and (0, 0) restores the default."""
+    torch = torch_cuda()
+    import paper_1612_09335_amd as C
+    mk, M, nv = SHAPE_CASES[case]
+    m = mk()
+    lm = C.Mesh(m.vertices, m.cells, M, periodic=m.box, ops="none", moving=True)
+    default = lm.moving_shape()
+    V = moved_vertices(m, 0.3, 0.15)
+    Q = _fields(dataclasses.replace(m, vertices=V), nv, 573)
+    t = lm.tables()
+    o = CwenoOracle(V, m.cells, m.box, Options(degree=M), stencils=(t["stencil"], t["sectors"]))
+    idx = np.unique(np.concatenate([np.arange(0, m.n_cells, 17), [m.n_cells - 1]]))
+    ref = o.reconstruct(Q, cells=idx)
+    st = t["stencil"][idx]
+    ran = []
+    for seg, rpl in SHAPES:
+        try:
+            lm.set_moving_shape(seg, rpl)
+        except C.CwenoError:
+            # too small for the stencil, or a shape the library does not build:
+            # rows of R outside the row slots, three rows per lane off 8 lanes,
+            # four rows per lane on 32 or 64 lanes, two rows per lane on 64
+            # lanes below 3-D degree 2
+            not_built = (lm.n_basis - 1 >= seg * rpl or (rpl == 3 and seg != 8) or (rpl == 4 and seg > 16)
+                         or (seg == 64 and rpl == 2 and not (lm.dim == 3 and M >= 2)))
+            assert seg * rpl < lm.n_e - 1 or not_built, (seg, rpl)
+            continue
+        assert lm.moving_shape() == (seg, rpl)
+        print(f"[gpu moving shapes] {case}: seg {seg} rpl {rpl}", flush=True)
+        r64 = _run_moving(torch, lm, V, Q, torch.float64)
+        assert np.array_equal(r64["coeffs"][:, 0, :].view(np.int64), Q.view(np.int64))
+        sub = {k: r64[k][:, :, idx] for k in ("coeffs", "sigma", "omega")}
+        assert _compare(sub, ref, Q, st, TOL64) <= TOL64, (seg, rpl)
+        r32 = _run_moving(torch, lm, V, Q, torch.float32)
+        assert data_scaled_error(r32["coeffs"][:, :, idx], ref["coeffs"], Q, st) <= TOL32, (seg, rpl)
+        ran.append((seg, rpl))
+    assert default in ran and len(ran) >= 2
+    with pytest.raises(C.CwenoError):
+        lm.set_moving_shape(8, 5)
+    with pytest.raises(C.CwenoError):
+        lm.set_moving_shape(12, 1)
+    lm.set_moving_shape(0, 0)
+    assert lm.moving_shape() == default
