@@ -64,10 +64,12 @@ constexpr int kMoveThreads = 256;  // four waves per block
 // waves (254 registers, 4 spills); with four (16 lanes per cell) they take
 // the accumulation registers as well and run one wave of four cells, which
 // measured 7% faster than two waves of two cells.  The 3-D degree-4 kernels
-// need all 256 and would spill heavily; the others fit three or four waves
-// unbounded.
+// need all 256 and would spill heavily.  The 2-D kernels are held to three
+// waves up to degree 3 and to two at degree 4 (on 8 lanes each would
+// otherwise take a few registers more than that allows and lose a wave:
+// measured 0.57 against 0.42 ms at degree 4); the others fit unbounded.
 __host__ __device__ constexpr int move_min_waves(int D, int M, int RPL) {
-  return D == 3 && M == 3 ? (RPL == 1 ? 3 : RPL == 2 ? 2 : 1) : 1;
+  return D == 3 ? (M == 3 ? (RPL == 1 ? 3 : RPL == 2 ? 2 : 1) : 1) : M <= 3 ? 3 : 2;
 }
 
 template <typename T>
@@ -493,6 +495,15 @@ struct GMTable {
 
 // ---------------------------------------------------------------- geometry
 
+// Vertices X of a cell moved to their minimum images around vertex 0.
+template <int D, typename T>
+__device__ __forceinline__ void unwrap_vertices(const MParams<T>& p, double (&X)[D + 1][D]) {
+#pragma unroll
+  for (int v = 1; v <= D; ++v)
+#pragma unroll
+    for (int a = 0; a < D; ++a) X[v][a] = X[0][a] + min_image_d(X[v][a] - X[0][a], p.box[a], p.ibox[a]);
+}
+
 // Vertices of cell c, each moved to its minimum image around vertex 0.
 template <int D, typename T>
 __device__ __forceinline__ void cell_vertices(const MParams<T>& p, int64_t c, double (&X)[D + 1][D]) {
@@ -503,10 +514,7 @@ __device__ __forceinline__ void cell_vertices(const MParams<T>& p, int64_t c, do
   for (int v = 0; v <= D; ++v)
 #pragma unroll
     for (int a = 0; a < D; ++a) X[v][a] = p.V[(int64_t)id[v] * D + a];
-#pragma unroll
-  for (int v = 1; v <= D; ++v)
-#pragma unroll
-    for (int a = 0; a < D; ++a) X[v][a] = X[0][a] + min_image_d(X[v][a] - X[0][a], p.box[a], p.ibox[a]);
+  unwrap_vertices<D>(p, X);
 }
 
 template <int D>
@@ -571,22 +579,52 @@ void moving_kernel(MParams<T> p) {
     barycentre<D>(X, ci);
   }
 
-  // 2. rows of A': averages of psi_1 .. psi_NL over the stencil cells
+  // 2. rows of A': averages of psi_1 .. psi_NL over the stencil cells.  The
+  // gathers of all the lane's rows go out level by level (stencil ids, vertex
+  // ids, positions) before any row is integrated, so that the lane waits once
+  // per level rather than once per level and row (a row slot past the
+  // stencil gathers the cell itself).  With rules of up to 5 points the rows
+  // are integrated without a branch and a slot past the stencil is zeroed
+  // afterwards, so that the scheduler may interleave them; the larger rules
+  // of M = 4 skip such a slot, one row at a time (interleaved, their rows
+  // would not fit the registers).
+  constexpr bool kRowBranch = GMRule<D, M>::NQ > 5;
   int row[RPL];
   bool rv[RPL];
   int32_t jr[RPL];
   double A[RPL][NL];
+  double XR[RPL][NS][D];
+  {
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      row[t] = sl + SEG * t;
+      rv[t] = row[t] < NE1;
+      jr[t] = rv[t] ? p.S0[ic * p.n_e + row[t] + 1] : (int32_t)ic;
+    }
+    int32_t vid[RPL][NS];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t)
+#pragma unroll
+      for (int v = 0; v < NS; ++v) vid[t][v] = p.C[(int64_t)jr[t] * NS + v];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t)
+#pragma unroll
+      for (int v = 0; v < NS; ++v)
+#pragma unroll
+        for (int a = 0; a < D; ++a) XR[t][v][a] = p.V[(int64_t)vid[t][v] * D + a];
+  }
   auto row_t = [&](auto tc) {
     constexpr int t = decltype(tc)::value;
-    row[t] = sl + SEG * t;
-    rv[t] = row[t] < NE1;
-    jr[t] = rv[t] ? p.S0[ic * p.n_e + row[t] + 1] : (int32_t)ic;
     double a[NL];
 #pragma unroll
     for (int l = 0; l < NL; ++l) a[l] = 0.0;
-    if (rv[t]) {
+    if (!kRowBranch || rv[t]) {
       double X[NS][D], cj[D], sh[D], Y[NS][D];
-      cell_vertices<D>(p, jr[t], X);
+#pragma unroll
+      for (int v = 0; v < NS; ++v)
+#pragma unroll
+        for (int b = 0; b < D; ++b) X[v][b] = XR[t][v][b];
+      unwrap_vertices<D>(p, X);
       barycentre<D>(X, cj);
 #pragma unroll
       for (int a = 0; a < D; ++a) {
@@ -619,8 +657,7 @@ void moving_kernel(MParams<T> p) {
         }
       }
       using GM = GMTable<D, M>;
-#pragma unroll
-      for (int qq = 0; qq < GMRule<D, M>::NQ; ++qq) {
+      auto point = [&](int qq) {
         double xi[D];
 #pragma unroll
         for (int r = 0; r < D; ++r) xi[r] = 0.0;
@@ -629,13 +666,36 @@ void moving_kernel(MParams<T> p) {
 #pragma unroll
           for (int r = 0; r < D; ++r) xi[r] = fma(GM::v.lam[qq][v], Y[v][r], xi[r]);
         basis_accumulate<D, M>(xi, GM::v.w[qq], a);
+      };
+      // rules of up to 10 points unrolled (their points become immediates);
+      // the 15-point rule of 3-D M = 4 stays a loop, whose unrolled body
+      // would spill to scratch memory
+      if constexpr (GMRule<D, M>::NQ <= 10) {
+#pragma unroll
+        for (int qq = 0; qq < GMRule<D, M>::NQ; ++qq) point(qq);
+      } else {
+#pragma unroll 1
+        for (int qq = 0; qq < GMRule<D, M>::NQ; ++qq) point(qq);
       }
       basis_normalise<D, M>(a);
     }
 #pragma unroll
-    for (int l = 0; l < NL; ++l) A[t][l] = a[l];
+    for (int l = 0; l < NL; ++l) A[t][l] = kRowBranch || rv[t] ? a[l] : 0.0;
   };
   StaticFor<0, RPL>::run(row_t);
+
+  // the sector stencil of sector sl (its cells and their rows in the central
+  // stencil), gathered here so that the latency overlaps the QR; lanes past
+  // the sectors read sector 0's and do not use it
+  int32_t ssr[NS];
+  int spr[D];
+  {
+    const int64_t at = ic * NS + (sl < NS ? sl : 0);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) ssr[k] = p.SS[at * NS + k];
+#pragma unroll
+    for (int a = 0; a < D; ++a) spr[a] = p.SP[at * D + a];
+  }
 
   // 3a. unit column norms
   {
@@ -723,7 +783,6 @@ void moving_kernel(MParams<T> p) {
   bool kept = false;
   if (sl < NS) {
     const int s = sl;
-    const int32_t* ss = p.SS + (ic * NS + s) * NS;
     double Bi[D][D];
 #pragma unroll
     for (int l = 0; l < D; ++l)
@@ -732,14 +791,13 @@ void moving_kernel(MParams<T> p) {
     int32_t sj[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) sj[a] = (int32_t)ic;
-    if (ss[0] >= 0) {
+    if (ssr[0] >= 0) {
       double B[D][D];
-      const uint8_t* sp = p.SP + (ic * NS + s) * D;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        sj[a] = ss[a + 1];
+        sj[a] = ssr[a + 1];
         double xi[D];
-        const int pos = sp[a];
+        const int pos = spr[a];
         if (pos != 255) {   // a central-stencil cell: its row lane left the barycentre in LDS
 #pragma unroll
           for (int r = 0; r < D; ++r) xi[r] = L[OXI + pos * D + r];
@@ -903,6 +961,22 @@ void moving_kernel(MParams<T> p) {
 #pragma unroll
       for (int t = 0; t < RPL; ++t) dq[t][v] = (act && rv[t]) ? (double)qv[jr[t]] - qi : 0.0;
     }
+    // the blend lane's own average and its sector cells' averages: gathered
+    // before the reflections where the kernel runs one wave per SIMD (the
+    // 3-D degree >= 3 shapes, whose latency no other wave hides), else at
+    // the blend (the registers they would hold meanwhile cost a wave)
+    constexpr bool kEarly = D == 3 && M >= 3;
+    T qiT = T(0);
+    double qsec[NS][D];
+    auto gather_blend = [&](int v) {
+      const T* qv = p.q + (int64_t)v * nc;
+      qiT = qv[ic];
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int a = 0; a < D; ++a) qsec[s][a] = (double)qv[LJ[s * D + a]];
+    };
+    if constexpr (kEarly) gather_blend(v0 + (sl < nvb ? sl : 0));
     auto reflect = [&](auto kc) {
       constexpr int k = decltype(kc)::value;
       const double tau = L[OTAU + k];
@@ -954,8 +1028,7 @@ void moving_kernel(MParams<T> p) {
     __syncthreads();
     if (valid && sl < nvb) {
       const int v = v0 + sl;
-      const T* qv = p.q + (int64_t)v * nc;
-      const T qiT = qv[i];
+      if constexpr (!kEarly) gather_blend(v);
       const double qi = (double)qiT;
       double po[NL];
 #pragma unroll
@@ -966,7 +1039,7 @@ void moving_kernel(MParams<T> p) {
       for (int s = 0; s < NS; ++s) {
         double dqs[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a) dqs[a] = (double)qv[LJ[s * D + a]] - qi;
+        for (int a = 0; a < D; ++a) dqs[a] = qsec[s][a] - qi;
 #pragma unroll
         for (int l = 0; l < D; ++l) {
           double x = 0.0;
