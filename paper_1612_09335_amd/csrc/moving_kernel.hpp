@@ -214,6 +214,17 @@ __device__ __forceinline__ double seg_bcast(double x, int seg) {
   }
 }
 
+// Orders the LDS accesses of the lanes of one wave: a wave-scope release
+// fence, a wave barrier and an acquire fence.  Every per-cell LDS record is
+// written and read by the lanes of its own segment, and a segment never spans
+// two waves, so no workgroup barrier is needed (with one wave per SIMD, one
+// would hold all four SIMDs of a workgroup to its slowest wave).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- small dense algebra
 
 // 1/x for finite non-zero x whose reciprocal is a normal number (either sign):
@@ -778,7 +789,7 @@ void moving_kernel(MParams<T> p) {
   };
   StaticFor<0, NL>::run(qr_step);
 
-  __syncthreads();   // the row cells' barycentres in LDS
+  wave_sync();   // the row cells' barycentres in LDS
   // 4. sectors: lane s of the segment builds and inverts sector s
   bool kept = false;
   if (sl < NS) {
@@ -852,7 +863,7 @@ void moving_kernel(MParams<T> p) {
     for (int a = 0; a < D; ++a) LJ[s * D + a] = sj[a];
   }
   const unsigned kmask = (unsigned)(__ballot(kept) >> (seg * SEG)) & ((1u << NS) - 1u);
-  __syncthreads();
+  wave_sync();
 
   // linear weights of the cell: dropped sectors get 0, the rest renormalised
   double lam[NS + 1];
@@ -916,7 +927,7 @@ void moving_kernel(MParams<T> p) {
       StaticFor<0, (NL + CH - 1) / CH>::run(chunk);
     };
     StaticFor<0, NL>::run(orth);
-    __syncthreads();
+    wave_sync();
     // column r of the pseudo-inverse: D^-1 R^-1 (row r of Q1)^T
     if (valid && row[0] < NE1) {
       auto back = [&](auto kc) {
@@ -1025,7 +1036,7 @@ void moving_kernel(MParams<T> p) {
 #pragma unroll
         for (int v = 0; v < VB; ++v) L[OP + v * NL + row[t]] = dq[t][v] * f;
       }
-    __syncthreads();
+    wave_sync();
     if (valid && sl < nvb) {
       const int v = v0 + sl;
       if constexpr (!kEarly) gather_blend(v);
@@ -1126,7 +1137,7 @@ void moving_kernel(MParams<T> p) {
         for (int s = 0; s <= NS; ++s) g[(int64_t)s * nc] = (T)om[s];
       }
     }
-    __syncthreads();
+    wave_sync();
   }
   }
   if (fault && valid && p.fault) atomicOr(p.fault, fault);
