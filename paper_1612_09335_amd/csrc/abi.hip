@@ -74,6 +74,39 @@ cweno_status upload(DevBuf& b, const void* src, size_t bytes, hipStream_t s, int
   return CWENO_OK;
 }
 
+// The classical WENO operators [row group g][entry l][Np] (g = j NE1 + k)
+// uploaded in the kernel's tiled order: within each row group, the NL entries
+// of a tile of cells are contiguous.  One row group at a time passes through a
+// host staging buffer.
+cweno_status upload_weno_tiled(DevBuf& b, const std::vector<double>& pinv, int64_t Np, int NL, hipStream_t s,
+                               int64_t& total) {
+  const size_t bytes = pinv.size() * sizeof(double), group = (size_t)NL * (size_t)Np;
+  if (bytes == 0) return CWENO_OK;
+  if (Np % cweno::kWenoTile != 0 || pinv.size() % group != 0) return fail(CWENO_E_ARG, "WENO operator size mismatch");
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return fail(CWENO_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  total += (int64_t)bytes;
+  std::vector<double> tile(group);
+  constexpr int64_t T = cweno::kWenoTile;
+  for (size_t g0 = 0; g0 < pinv.size(); g0 += group) {
+    const double* src = pinv.data() + g0;
+    cweno::parallel_for(Np / T, [&](int64_t t0, int64_t t1) {
+      for (int64_t t = t0; t < t1; ++t)
+        for (int l = 0; l < NL; ++l)
+          for (int64_t c = 0; c < T; ++c) tile[((size_t)t * NL + l) * T + c] = src[(size_t)l * Np + t * T + c];
+    });
+    e = hipMemcpyAsync(static_cast<double*>(b.p) + g0, tile.data(), group * sizeof(double), hipMemcpyHostToDevice, s);
+    // pageable source: wait before the staging buffer is refilled
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("WENO operator upload failed: ") + hipGetErrorString(e));
+  }
+  return CWENO_OK;
+}
+
 cweno_status alloc_zero(DevBuf& b, size_t bytes, hipStream_t s, int64_t& total) {
   hipError_t e = hipMalloc(&b.p, bytes);
   if (e != hipSuccess) {
@@ -228,19 +261,20 @@ cweno_status reconstruct_weno(const cweno_mesh* m, int n_vars, cweno_dtype dtype
   p.NE1 = m->n_e - 1;
   p.n_s = m->n_s;
   p.r = m->r;
-  // a pass takes up to kWenoMaxGroup * vbmax variables (G lanes per cell with
-  // VB each, VB as even as the count allows), and no more than the LDS holds
-  // for the longest block halo
+  // a pass takes up to kWenoMaxGroup * vbmax variables (G lanes per cell, a
+  // power of two, with VB each), and no more than the LDS holds for the
+  // longest block halo
   const int vbmax = cweno::weno_vb_max(m->d, m->M);
   const int lds_vars = (int)(cweno::kWenoMaxLds / ((size_t)m->wmaxH * sizeof(double)));
   const int per_pass = std::min(cweno::kWenoMaxGroup * vbmax, lds_vars);
   for (int v0 = 0; v0 < n_vars;) {
     const int n = std::min(n_vars - v0, per_pass);
-    const int g0 = (n + vbmax - 1) / vbmax;
-    const int vb = (n + g0 - 1) / g0;
+    int g = 1;
+    while (g * vbmax < n) g *= 2;
+    const int vb = (n + g - 1) / g;
     p.v0 = v0;
     p.v1 = v0 + n;
-    p.G = (n + vb - 1) / vb;
+    p.G = g;
     const hipError_t e = cweno::launch_weno(m->d, m->M, p, vb, m->wmaxH, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(CWENO_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     v0 += n;
@@ -371,7 +405,7 @@ cweno_status cweno_mesh_create(int dim, int64_t n_vertices, const double* vertic
         hipStream_t s = (hipStream_t)hip_stream;
         if (hipGetDevice(&m->device) != hipSuccess) return fail(CWENO_E_HIP, "no HIP device");
         cweno_status ust;
-        if ((ust = upload(m->wpinv, wop.pinv.data(), wop.pinv.size() * 8, s, m->device_bytes))) return ust;
+        if ((ust = upload_weno_tiled(m->wpinv, wop.pinv, wop.Np, m->nb - 1, s, m->device_bytes))) return ust;
         if ((ust = upload(m->walive, wop.alive.data(), wop.alive.size() * 2, s, m->device_bytes))) return ust;
         if ((ust = upload(m->wlidx, wh.lidx.data(), wh.lidx.size() * 2, s, m->device_bytes))) return ust;
         if ((ust = upload(m->whalo, wh.cells.data(), wh.cells.size() * 4, s, m->device_bytes))) return ust;

@@ -18,11 +18,18 @@
 // 2 (nb-1) VB accumulators, which limits VB to 4 / 2 / 1 for nb-1 up to
 // 9 / 19 / 34.  The lanes of a group load the same operator entries in the
 // same instruction, so the wave fetches each entry once per pass; operator
-// rows stream with a non-temporal policy.
+// rows stream with a non-temporal policy.  The rows of a stencil go in
+// chunks of KC, double-buffered: the halo positions and operator rows of the
+// next chunk are requested before the current one is used, so that a wave
+// keeps up to 2 KC rows of loads in flight instead of waiting a memory round
+// trip per row (the block halos hold about 13 cells per cell, so LDS allows
+// only a few waves per SIMD and each must carry many loads).
 //
 // LDS layout: [halo cell][variable of the pass], the variables of a cell
 // together.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "mesh.hpp"
 #include "reconstruct_kernel.hpp"
@@ -30,13 +37,64 @@
 
 namespace cweno {
 
-template <int D, int M, int VB>
+// f(std::integral_constant<int, I>) for I = 0 .. N-1 (compile-time indices).
+template <int I, int N>
+struct StaticForW {
+  template <typename F>
+  __device__ __forceinline__ static void run(F& f) {
+    f(std::integral_constant<int, I>{});
+    StaticForW<I + 1, N>::run(f);
+  }
+};
+template <int N>
+struct StaticForW<N, N> {
+  template <typename F>
+  __device__ __forceinline__ static void run(F&) {}
+};
+
+// Value of x in lane SRC of this lane's group of G consecutive lanes (G = 1,
+// 2, 4 or 8; a group never crosses a DPP row): quad permutations for pairs
+// and quads; for 8 lanes the quad holding lane SRC is then copied to the
+// group's other quad by a 4-lane row shift written to that quad's banks.
+template <int G, int SRC>
+__device__ __forceinline__ double group_bcast(double x) {
+  static_assert(SRC >= 0 && SRC < G, "lane of the group");
+  auto dpp = [](double y, auto ctrl, auto banks, double old) {
+    constexpr int C = decltype(ctrl)::value, B = decltype(banks)::value;
+    const uint64_t u = __builtin_bit_cast(uint64_t, y), o = __builtin_bit_cast(uint64_t, old);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)u, C, 0xF, B, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(u >> 32), C, 0xF, B, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  };
+  if constexpr (G == 1) {
+    return x;
+  } else if constexpr (G == 2) {
+    return dpp(x, std::integral_constant<int, SRC | SRC << 2 | (2 + SRC) << 4 | (2 + SRC) << 6>{},
+               std::integral_constant<int, 0xF>{}, x);
+  } else if constexpr (G == 4) {
+    return dpp(x, std::integral_constant<int, SRC * 0x55>{}, std::integral_constant<int, 0xF>{}, x);
+  } else {
+    static_assert(G == 8, "groups of 1, 2, 4 or 8 lanes");
+    const double a = dpp(x, std::integral_constant<int, (SRC % 4) * 0x55>{}, std::integral_constant<int, 0xF>{}, x);
+    if constexpr (SRC < 4)
+      return dpp(a, std::integral_constant<int, 0x114>{}, std::integral_constant<int, 0xA>{}, a);   // row_shr:4
+    else
+      return dpp(a, std::integral_constant<int, 0x104>{}, std::integral_constant<int, 0x5>{}, a);   // row_shl:4
+  }
+}
+
+template <int D, int M, int VB, int G>
 __global__ __launch_bounds__(kWenoBlockCells * kWenoMaxGroup) void weno_kernel(WParams p) {
   constexpr int NB = nbasis_c(M, D);
   constexpr int NL = NB - 1;
+  constexpr int NT = (NL + G - 1) / G;                  // entries of a row each lane of a group loads
+  constexpr int KC = weno_kc(D, M, VB, G);
+  constexpr int KB = KC > 0 ? KC : 1;
+  constexpr int T = kWenoTile;
   extern __shared__ double lq[];
   const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
-  const int G = p.G, nvp = p.v1 - p.v0;
+  const int nvp = p.v1 - p.v0;
   const int64_t nc = p.nc, Np = p.Np;
   const int64_t b = xcd_block(blockIdx.x, gridDim.x);
 
@@ -50,22 +108,25 @@ __global__ __launch_bounds__(kWenoBlockCells * kWenoMaxGroup) void weno_kernel(W
   }
   __syncthreads();
 
+  // every lane of a group stays to the end: it loads its share of each row
+  // for the others; a cell past the mesh works on the last cell and stores
+  // nothing, a lane without variables repeats the pass's last one
   const int cw = tid / G, sub = tid - cw * G;
   const int64_t i = b * kWenoBlockCells + cw;
-  if (i >= nc) return;
+  const bool live = i < nc;
+  const int64_t ic = live ? i : nc - 1;
   const int vofs = sub * VB;                            // this lane's first variable within the pass
-  const int nvl = min(VB, nvp - vofs);                  // and how many it owns
-  if (nvl <= 0) return;
+  const int nvl = min(VB, nvp - vofs);                  // and how many it owns (may be none)
   const int NE1 = p.NE1, n_s = p.n_s;
-  const uint16_t* li = p.lidx + i;
-  int vv[VB];                                           // LDS column of each variable (the last repeated)
+  const uint16_t* li = p.lidx + ic;
+  int vv[VB];                                           // LDS column of each variable
 #pragma unroll
-  for (int v = 0; v < VB; ++v) vv[v] = vofs + min(v, nvl - 1);
+  for (int v = 0; v < VB; ++v) vv[v] = min(vofs + v, nvp - 1);
   const double* ls = lq + (int)li[(int64_t)n_s * NE1 * Np] * nvp;
   double qi[VB];
 #pragma unroll
   for (int v = 0; v < VB; ++v) qi[v] = ls[vv[v]];
-  const unsigned am = p.alive[i];
+  const unsigned am = p.alive[ic];
   double lsum = 0.0;
   for (int j = 0; j < n_s; ++j)
     if ((am >> j) & 1u) lsum += j == 0 ? p.lam0 : p.lams;
@@ -77,26 +138,64 @@ __global__ __launch_bounds__(kWenoBlockCells * kWenoMaxGroup) void weno_kernel(W
     for (int l = 0; l < NL; ++l) wn[l][v] = 0.0;
   }
   for (int j = 0; j < n_s; ++j) {
-    if (!((am >> j) & 1u)) continue;
+    if (!((am >> j) & 1u)) continue;                    // the same for every lane of a group
     const double lj = (j == 0 ? p.lam0 : p.lams) / lsum;
     double acc[NL][VB];
 #pragma unroll
     for (int l = 0; l < NL; ++l)
 #pragma unroll
       for (int v = 0; v < VB; ++v) acc[l][v] = 0.0;
-    const double* pj = p.pinv + (int64_t)j * NE1 * NL * Np + i;
+    const double* pj = p.pinv + (int64_t)j * NE1 * NL * Np + (ic / T) * NL * T + ic % T;
     const uint16_t* lj16 = li + (int64_t)j * NE1 * Np;
-    for (int k = 0; k < NE1; ++k) {
-      const double* lh = lq + (int)lj16[(int64_t)k * Np] * nvp;
-      double dq[VB];
+    // lane sub of a group loads entries sub, sub + G, ... of a row (distinct
+    // addresses across the group) and the group shares them by lane
+    // broadcasts; chunk c+1's requests go out before chunk c is used (two
+    // chunks of rows in registers), so that a wave always has loads in flight
+    int hp[2][KB];
+    double r[2][KB][NT];
+    auto request = [&](int bf, int k0) {
 #pragma unroll
-      for (int v = 0; v < VB; ++v) dq[v] = lh[vv[v]] - qi[v];
-      const double* pk = pj + (int64_t)k * NL * Np;
+      for (int u = 0; u < KB; ++u) {
+        const int k = min(k0 + u, NE1 - 1);             // past the stencil: its last row again, not used
+        hp[bf][u] = lj16[(int64_t)k * Np];
+        const double* pk = pj + (int64_t)k * NL * Np;
 #pragma unroll
-      for (int l = 0; l < NL; ++l) {
-        const double r = __builtin_nontemporal_load(pk + (int64_t)l * Np);
+        for (int t = 0; t < NT; ++t) r[bf][u][t] = __builtin_nontemporal_load(pk + min(sub + G * t, NL - 1) * T);
+      }
+    };
+    auto consume = [&](int bf, int k0) {
 #pragma unroll
-        for (int v = 0; v < VB; ++v) acc[l][v] = fma(r, dq[v], acc[l][v]);
+      for (int u = 0; u < KB; ++u) {
+        if (k0 + u >= NE1) break;
+        const double* lh = lq + hp[bf][u] * nvp;
+        double dq[VB];
+#pragma unroll
+        for (int v = 0; v < VB; ++v) dq[v] = lh[vv[v]] - qi[v];
+        auto entry = [&](auto lc) {
+          constexpr int l = decltype(lc)::value;
+          const double x = group_bcast<G, l % G>(r[bf][u][l / G]);
+#pragma unroll
+          for (int v = 0; v < VB; ++v) acc[l][v] = fma(x, dq[v], acc[l][v]);
+        };
+        StaticForW<0, NL>::run(entry);
+      }
+    };
+    if constexpr (KC > 0) {
+      request(0, 0);
+      for (int k0 = 0; k0 < NE1; k0 += 2 * KC) {
+        // the barriers keep each chunk's requests ahead of the other's uses
+        // (the scheduler would sink every row's loads to its multiply-adds)
+        if (k0 + KC < NE1) request(1, k0 + KC);
+        __builtin_amdgcn_sched_barrier(0);
+        consume(0, k0);
+        if (k0 + 2 * KC < NE1) request(0, k0 + 2 * KC);
+        __builtin_amdgcn_sched_barrier(0);
+        if (k0 + KC < NE1) consume(1, k0 + KC);
+      }
+    } else {
+      for (int k = 0; k < NE1; ++k) {
+        request(0, k);
+        consume(0, k);
       }
     }
 #pragma unroll
@@ -112,6 +211,7 @@ __global__ __launch_bounds__(kWenoBlockCells * kWenoMaxGroup) void weno_kernel(W
       for (int l = 0; l < NL; ++l) wn[l][v] = fma(wt, acc[l][v], wn[l][v]);
     }
   }
+  if (!live) return;
 #pragma unroll
   for (int v = 0; v < VB; ++v) {
     if (v >= nvl) break;
@@ -128,21 +228,33 @@ namespace {
 template <int D, int M>
 hipError_t launch_dm(const WParams& p, int vb, int max_halo, hipStream_t s) {
   const int nvp = p.v1 - p.v0;
-  if (p.G < 1 || p.G > kWenoMaxGroup || nvp < 1 || nvp > p.G * vb) return hipErrorInvalidValue;
+  if ((p.G != 1 && p.G != 2 && p.G != 4 && p.G != 8) || nvp < 1 || nvp > p.G * vb) return hipErrorInvalidValue;
   const size_t lds = (size_t)max_halo * (size_t)nvp * sizeof(double);
   if (lds > kWenoMaxLds) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)((p.nc + kWenoBlockCells - 1) / kWenoBlockCells);
   const unsigned threads = (unsigned)(kWenoBlockCells * p.G);
+  auto go = [&](auto vbc, auto gc) -> hipError_t {
+    constexpr int V = decltype(vbc)::value, G = decltype(gc)::value;
+    if constexpr (V <= weno_vb_max(D, M)) {
+      hipLaunchKernelGGL((weno_kernel<D, M, V, G>), dim3(blocks), dim3(threads), lds, s, p);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  };
+  auto by_g = [&](auto vbc) -> hipError_t {
+    switch (p.G) {
+      case 1: return go(vbc, std::integral_constant<int, 1>{});
+      case 2: return go(vbc, std::integral_constant<int, 2>{});
+      case 4: return go(vbc, std::integral_constant<int, 4>{});
+      case 8: return go(vbc, std::integral_constant<int, 8>{});
+    }
+    return hipErrorInvalidValue;
+  };
   switch (vb) {
-#define CWENO_WENO_VB(V)                                                                                         \
-  case V:                                                                                                        \
-    if constexpr (V <= weno_vb_max(D, M)) {                                                                      \
-      hipLaunchKernelGGL((weno_kernel<D, M, V>), dim3(blocks), dim3(threads), lds, s, p);                         \
-      return hipGetLastError();                                                                                  \
-    }                                                                                                            \
-    break;
-    CWENO_WENO_VB(1) CWENO_WENO_VB(2) CWENO_WENO_VB(3) CWENO_WENO_VB(4)
-#undef CWENO_WENO_VB
+    case 1: return by_g(std::integral_constant<int, 1>{});
+    case 2: return by_g(std::integral_constant<int, 2>{});
+    case 3: return by_g(std::integral_constant<int, 3>{});
+    case 4: return by_g(std::integral_constant<int, 4>{});
   }
   return hipErrorInvalidValue;
 }
