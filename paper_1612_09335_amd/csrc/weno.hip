@@ -6,24 +6,27 @@
 // with the universal Sigma; omega~_j = lambda_j / (sigma_j + eps)^r;
 // w = sum_j omega~_j P_j / sum_j omega~_j (eqs. weights, weights2).
 //
-// A workgroup takes kWenoBlockCells consecutive cells with a group of G lanes
-// per cell (G <= 8), each lane reconstructing VB of the pass's variables.  It
-// first copies the averages of its halo -- the sorted unique cells its
-// stencils reference, listed on the host -- for every variable of the pass
-// into LDS, then reads every stencil difference from LDS through 16-bit
-// halo positions: the 1 + 2(d+1) stencils of a cell overlap, and neighbouring
-// cells share most of them, so each average comes from HBM once per block.
-// Every stencil's polynomial is needed whole before its weight is known, so a
-// lane keeps the polynomial being formed and the weighted running sum:
-// 2 (nb-1) VB accumulators, which limits VB to 4 / 2 / 1 for nb-1 up to
-// 9 / 19 / 34.  The lanes of a group load the same operator entries in the
-// same instruction, so the wave fetches each entry once per pass; operator
-// rows stream with a non-temporal policy.  The rows of a stencil go in
-// chunks of KC, double-buffered: the halo positions and operator rows of the
-// next chunk are requested before the current one is used, so that a wave
-// keeps up to 2 KC rows of loads in flight instead of waiting a memory round
-// trip per row (the block halos hold about 13 cells per cell, so LDS allows
-// only a few waves per SIMD and each must carry many loads).
+// A workgroup takes kWenoBlockCells consecutive cells with a group of G = 1,
+// 2, 4 or 8 lanes per cell, each lane reconstructing VB of the pass's
+// variables.  It first copies the averages of its halo -- the sorted unique
+// cells its stencils reference, listed on the host -- for every variable of
+// the pass into LDS, then reads every stencil difference from LDS through
+// 16-bit halo positions: the 1 + 2(d+1) stencils of a cell overlap, and
+// neighbouring cells share most of them, so each average comes from HBM once
+// per block.  Every stencil's polynomial is needed whole before its weight is
+// known, so a lane keeps the polynomial being formed and the weighted running
+// sum: 2 (nb-1) VB accumulators, which limits VB to 4 / 2 / 1 for nb-1 up to
+// 9 / 19 / 34.  Lane s of a group loads entries s, s + G, ... of each
+// operator row (a wave's load instruction returns 64 distinct values; when
+// every lane of a group loaded every entry, the duplicates set the time) and
+// the group shares them by lane broadcasts; operator rows stream with a
+// non-temporal policy, tiled so that a row's entries for 16 cells are one
+// contiguous run.  The rows of a stencil go in chunks of KC,
+// double-buffered: the halo positions and operator entries of the next chunk
+// are requested before the current one is used, so that a wave keeps up to
+// 2 KC rows of loads in flight instead of waiting a memory round trip per row
+// (the block halos hold about 13 cells per cell, so LDS allows only a few
+// waves per SIMD and each must carry many loads).
 //
 // LDS layout: [halo cell][variable of the pass], the variables of a cell
 // together.
