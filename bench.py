@@ -448,7 +448,8 @@ def measure_serving(torch, C, seconds, rate=2000.0, n_meshes=200, lo=2e3, hi=5e4
     footprint (the FP32 operators fit, the FP64 ones, twice as large, do not), Poisson
     arrivals; every mesh is requested once before the timed runs.  FP32 at the
     nominal rate with requests batched as they arrive, then a sweep of arrival
-    rates with and without batching; FP64 (evicting) and a serial FP64 server."""
+    rates with and without batching; FP64 (evicting), a serial FP64 server, and
+    FP64 under a budget of 1.1 times its own footprint (resident)."""
     from synthetic import batch_spec, workload_mesh
     spec = batch_spec(n_meshes, lo, hi, seed=16120938)
     t0 = time.perf_counter()
@@ -476,8 +477,8 @@ def measure_serving(torch, C, seconds, rate=2000.0, n_meshes=200, lo=2e3, hi=5e4
     budget = int(budget_factor * foot32)
     log(f"serving: {n_meshes} meshes, {cells} cells, precompute {t_pre:.1f} s")
 
-    def server(dt, tdt, inflight, streams, batch):
-        srv = C.Server(budget, dtype=dt, max_inflight=inflight, n_streams=streams, max_batch=batch)
+    def server(dt, tdt, inflight, streams, batch, budget_bytes=None):
+        srv = C.Server(budget_bytes or budget, dtype=dt, max_inflight=inflight, n_streams=streams, max_batch=batch)
         ids = [srv.register_mesh(h) for h in hosts]
         qs = [torch.tensor(rng.normal(size=(nv, m.n_cells)), dtype=tdt, device="cuda:0") for m, _ in raw]
         outs = [torch.empty((nv, h.n_basis, h.n_cells), dtype=tdt, device="cuda:0") for h in hosts]
@@ -518,6 +519,14 @@ def measure_serving(torch, C, seconds, rate=2000.0, n_meshes=200, lo=2e3, hi=5e4
         out[tag] = r
         report(tag, r)
         del srv, qs, outs
+    # FP64 under a budget that holds every image: the FP64 served rate without eviction
+    b64 = int(1.1 * out["f64"]["footprint_gb"] * 1e9)
+    srv, ids, qs, outs = server("f64", torch.float64, 8, 8, 64, b64)
+    r = serve_run(torch, srv, ids, qs, outs, cv, *arrivals(rate, min(seconds, 3.0)))
+    r.update(footprint_gb=out["f64"]["footprint_gb"], budget_gb=b64 / 1e9, max_inflight=8, streams=8, max_batch=64)
+    out["f64_resident"] = r
+    report("f64 resident", r)
+    del srv, qs, outs
     return out
 
 
