@@ -6,7 +6,8 @@ stencils' column-scaled least-squares matrices reach condition numbers of
 about 8e3 (against 2e2 for the central stencils), and two backward-stable FP64
 solvers (Householder on the host, SVD in the oracle) then differ by up to a
 small multiple of u * kappa ~ 9e-13 of the data scale (measured on the degree-4
-case below: 1.3e-12);
+cases below: 1.3e-12 over two variables, 2.6e-12 over nine -- the operators,
+and so these errors, are the same whatever the lanes per cell);
 coefficient 0 bit for bit, cell counts leaving the last workgroup ragged and
 variable counts leaving the last variable block partly empty; end to end,
 the reconstruction of the exact averages of a degree-M polynomial evaluated
@@ -25,7 +26,11 @@ CASES = [("tri16_M2_nv5", lambda: tri_mesh(16, 0.15, 901), 2, 5, 0.95),
          ("tri20_M3_nv9", lambda: tri_mesh(20, 0.15, 902), 3, 9, 0.95),
          ("tri24_M4_nv2", lambda: tri_mesh(24, 0.15, 903), 4, 2, 0.95),
          ("tri16_M1_nv3_paper_lambda", lambda: tri_mesh(16, 0.15, 904), 1, 3, "paper"),
-         ("kuhn16_M2_nv5", lambda: kuhn_tet_mesh(16, 0.1, 905), 2, 5, 0.95)]
+         ("kuhn16_M2_nv5", lambda: kuhn_tet_mesh(16, 0.1, 905), 2, 5, 0.95),
+         # lane groups sharing the operator loads: 4 lanes over 19 entries a row
+         # (2 variables each), and 8 lanes over 14 (2 each, the last lane idle)
+         ("kuhn16_M3_nv5", lambda: kuhn_tet_mesh(16, 0.1, 907), 3, 5, 0.95),
+         ("tri24_M4_nv9", lambda: tri_mesh(24, 0.15, 908), 4, 9, 0.95)]
 
 
 @pytest.mark.parametrize("name,mk,M,nv,lam", CASES)
