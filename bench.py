@@ -204,7 +204,7 @@ def measure_weno(torch, C, m, Q, M, d, steps, cweno_ms, cweno_n_e):
          "paper_formula_ratio": paper_ratio,
          "algorithmic_byte_ratio_weno_over_cweno":
              alg / (algorithmic_bytes_per_cell(d, M, cweno_n_e, nv, 8) * m.n_cells),
-         "ms_per_step": ms, "value": m.n_cells * nv / (ms * 1e-3),
+         "ms_per_step": ms, "steps": steps, "value": m.n_cells * nv / (ms * 1e-3),
          "time_ratio_weno_over_cweno_f64": ms / cweno_ms, "operator_passes": passes,
          "comparison_note": "the algorithmic byte ratio is the schemes' comparison at equal streaming rates; "
                             "the time ratio also holds the two kernels' different fractions of HBM peak "
@@ -334,11 +334,23 @@ def measure(torch, C, m, Q, M, factor, steps, warmup, label, d, keep_out=False):
     return res
 
 
+WARM_S = 0.1
+
+
 def time_loop(torch, fn, steps, warmup):
-    """Average ms of fn() over `steps` back-to-back calls on the current stream."""
-    for _ in range(warmup):
-        fn()
-    torch.cuda.synchronize()
+    """Average ms of fn() over `steps` back-to-back calls on the current stream,
+    after at least `warmup` calls and at least WARM_S seconds of back-to-back
+    calls: the GPU idles while the host builds a workload, and the launches
+    right after such a pause run slower (those of a 1.4 ms kernel fell from
+    1.8 ms to 1.37 ms over the first 20, most likely while the clocks come
+    back up from idle)."""
+    t0 = time.perf_counter()
+    while True:
+        for _ in range(max(warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= WARM_S:
+            break
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):

@@ -70,16 +70,24 @@ __device__ __forceinline__ double group_bcast(double x) {
         (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(u >> 32), C, 0xF, B, false);
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
   };
+  // a quad permutation writes every lane from a lane of its own quad: no
+  // old value to keep, so none is copied into the destination first
+  auto perm = [](double y, auto ctrl) {
+    constexpr int C = decltype(ctrl)::value;
+    const uint64_t u = __builtin_bit_cast(uint64_t, y);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, C, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), C, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  };
   if constexpr (G == 1) {
     return x;
   } else if constexpr (G == 2) {
-    return dpp(x, std::integral_constant<int, SRC | SRC << 2 | (2 + SRC) << 4 | (2 + SRC) << 6>{},
-               std::integral_constant<int, 0xF>{}, x);
+    return perm(x, std::integral_constant<int, SRC | SRC << 2 | (2 + SRC) << 4 | (2 + SRC) << 6>{});
   } else if constexpr (G == 4) {
-    return dpp(x, std::integral_constant<int, SRC * 0x55>{}, std::integral_constant<int, 0xF>{}, x);
+    return perm(x, std::integral_constant<int, SRC * 0x55>{});
   } else {
     static_assert(G == 8, "groups of 1, 2, 4 or 8 lanes");
-    const double a = dpp(x, std::integral_constant<int, (SRC % 4) * 0x55>{}, std::integral_constant<int, 0xF>{}, x);
+    const double a = perm(x, std::integral_constant<int, (SRC % 4) * 0x55>{});
     if constexpr (SRC < 4)
       return dpp(a, std::integral_constant<int, 0x114>{}, std::integral_constant<int, 0xA>{}, a);   // row_shr:4
     else
