@@ -389,7 +389,22 @@ __device__ __forceinline__ void finish_variable(const KParams<T>& p, uint32_t io
     for (int l = 0; l < NL; ++l) w[l] = lw[l * kHaloBlockLanes];
     using cT = __attribute__((address_space(4))) const T;
     const cT* const phi = (const cT*)p.phi;
-    for (int q = 0; q < p.npts; ++q) {
+    // two points per step: the second point's basis values are requested
+    // with the first's, so one scalar-load round trip serves both
+    int q = 0;
+    for (; q + 1 < p.npts; q += 2) {
+      const cT* f = phi + q * NB;
+      const cT* g = f + NB;
+      T x = fma(f[0], qi, T(0)), y = fma(g[0], qi, T(0));
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        x = fma(f[l + 1], w[l], x);
+        y = fma(g[l + 1], w[l], y);
+      }
+      bst(rp, x, io, (uint32_t)q * crow);
+      bst(rp, y, io, (uint32_t)(q + 1) * crow);
+    }
+    if (q < p.npts) {
       const cT* f = phi + q * NB;
       T x = fma(f[0], qi, T(0));
 #pragma unroll
