@@ -110,12 +110,28 @@ __global__ __launch_bounds__(kWenoBlockCells * kWenoMaxGroup) void weno_kernel(W
   const int64_t b = xcd_block(blockIdx.x, gridDim.x);
 
   // stage the block's halo, cell-fastest so that runs of consecutive cells
-  // read consecutive addresses
-  const int h0 = p.hoff[b], hn = p.hoff[b + 1] - h0;
-  for (int hc = tid; hc < hn; hc += nthr) {
-    const int64_t c = p.halo[h0 + hc];
-    const double* qc = p.q + (int64_t)p.v0 * nc + c;
-    for (int v = 0; v < nvp; ++v) lq[hc * nvp + v] = qc[(int64_t)v * nc];
+  // read consecutive addresses; SU cells per thread at a time, so that each
+  // round is two memory round trips (positions, then averages)
+  {
+    constexpr int VMAX = VB * G;
+    constexpr int SU = VMAX >= 16 ? 1 : 32 / VMAX < 4 ? 32 / VMAX : 4;
+    const int h0 = p.hoff[b], hn = p.hoff[b + 1] - h0;
+    for (int hb = tid; hb < hn; hb += SU * nthr) {
+      int64_t c[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) c[u] = hb + u * nthr < hn ? p.halo[h0 + hb + u * nthr] : -1;
+      double x[SU][VMAX];
+#pragma unroll
+      for (int u = 0; u < SU; ++u)
+#pragma unroll
+        for (int v = 0; v < VMAX; ++v)
+          if (v < nvp && c[u] >= 0) x[u][v] = p.q[(int64_t)(p.v0 + v) * nc + c[u]];
+#pragma unroll
+      for (int u = 0; u < SU; ++u)
+#pragma unroll
+        for (int v = 0; v < VMAX; ++v)
+          if (v < nvp && c[u] >= 0) lq[(hb + u * nthr) * nvp + v] = x[u][v];
+    }
   }
   __syncthreads();
 
