@@ -11,10 +11,12 @@ namespace cweno {
 // Segment shapes (lanes per cell, rows per lane) instantiated for (D, M): the
 // rows of R must lie in the segment's row slots (fewer basis functions than
 // lanes times rows per lane), three rows per lane only on 8 lanes, four only
-// on 8 or 16, and two rows per lane on 64 lanes only for the wide 3-D
-// stencils.
+// on 8 or 16, two rows per lane on 64 lanes only for the wide 3-D stencils,
+// and 4 lanes of five rows each only for the 2-D degree-3 stencils (19 cells
+// besides the cell: 20 row slots against 24 on 8 lanes of three).
 __host__ __device__ constexpr bool move_shape_ok(int D, int M, int seg, int rpl) {
-  return (seg == 8 || seg == 16 || seg == 32 || seg == 64) && rpl >= 1 && rpl <= 4 &&
+  return ((seg == 4 && rpl == 5 && D == 2 && M == 3) ||
+          ((seg == 8 || seg == 16 || seg == 32 || seg == 64) && rpl >= 1 && rpl <= 4)) &&
          nbasis_c(M, D) - 1 < seg * rpl && (rpl != 3 || seg == 8) && (rpl < 4 || seg <= 16) &&
          (seg < 64 || rpl == 1 || (D == 3 && M >= 2));
 }
@@ -22,8 +24,8 @@ __host__ __device__ constexpr bool move_shape_ok(int D, int M, int seg, int rpl)
 // Preferred shapes, in order: the narrowest segment whose rows hold the
 // stencil, with as few rows per lane as that allows (fewer exchange stages per
 // sum, more cells per wave instruction).
-constexpr int kMoveShapes[11][2] = {{8, 1},  {8, 2},  {8, 3},  {8, 4},  {16, 1}, {16, 2},
-                                    {16, 4}, {32, 1}, {32, 2}, {64, 1}, {64, 2}};
+constexpr int kMoveShapes[12][2] = {{4, 5},  {8, 1},  {8, 2},  {8, 3},  {8, 4},  {16, 1},
+                                    {16, 2}, {16, 4}, {32, 1}, {32, 2}, {64, 1}, {64, 2}};
 
 // First instantiated shape whose rows hold the NE1 stencil cells besides the
 // cell (with one_row, among the shapes of one row per lane); false if none

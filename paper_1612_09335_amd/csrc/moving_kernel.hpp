@@ -5,7 +5,7 @@
 // at every step (Sec. 2.1), so storing them buys nothing; this trades the
 // operator stream for arithmetic.
 //
-// Work mapping.  A segment of SEG lanes (8, 16, 32 or 64) owns one cell.  Lane t
+// Work mapping.  A segment of SEG lanes (4, 8, 16, 32 or 64) owns one cell.  Lane t
 // of the segment owns rows t, t + SEG, ... (RPL rows) of the cell's least-
 // squares matrix A' (row k: stencil cell k+1).  Per cell:
 //   1. every lane unwraps the cell's vertices (minimum image around vertex 0)
@@ -19,7 +19,8 @@
 //      rows of 16 lanes, a swizzle across rows, lane reads across the halves
 //      of the wave), so a narrower segment with more rows per lane needs
 //      fewer exchange stages per sum and serves more cells per wave
-//      instruction.  Each reflector stays in the entries it eliminated;
+//      instruction (a sum of R rows per lane over S lanes costs R + 3 log2 S
+//      wave instructions for 64 / S cells).  Each reflector stays in the entries it eliminated;
 //   4. one lane per sector evaluates the linear basis functions at the sector
 //      cells' barycentres (the averages of a linear function), inverts the
 //      d x d system (eq. CWENO:Ps) and drops the sector if its 2-norm
@@ -46,14 +47,15 @@
 
 namespace cweno {
 
-// Variables reflected together (a pass): 2, 5 or 9; at most 5 where the
+// Variables reflected together (a pass): 2, 4, 5 or 9; at most 5 where the
 // basis has more than 15 functions (the register budget of the 3-D M >= 3
-// rows) and on 8-lane segments (one lane per variable forms the blend).
+// rows) and on 8-lane segments, 4 on 4-lane segments (one lane per variable
+// forms the blend).
 __host__ __device__ constexpr int move_vb_max(int D, int M, int SEG) {
-  return nbasis_c(M, D) - 1 <= 14 && SEG >= 9 ? 9 : 5;
+  return SEG == 4 ? 4 : nbasis_c(M, D) - 1 <= 14 && SEG >= 9 ? 9 : 5;
 }
 __host__ __device__ constexpr int move_vb(int D, int M, int SEG, int nv) {
-  return nv <= 2 ? 2 : (nv <= 5 || move_vb_max(D, M, SEG) == 5) ? 5 : 9;
+  return nv <= 2 ? 2 : SEG == 4 ? 4 : (nv <= 5 || move_vb_max(D, M, SEG) == 5) ? 5 : 9;
 }
 constexpr int kMoveThreads = 256;  // four waves per block
 
@@ -67,9 +69,11 @@ constexpr int kMoveThreads = 256;  // four waves per block
 // need all 256 and would spill heavily.  The 2-D kernels are held to three
 // waves up to degree 3 and to two at degree 4 (on 8 lanes each would
 // otherwise take a few registers more than that allows and lose a wave:
-// measured 0.57 against 0.42 ms at degree 4); the others fit unbounded.
+// measured 0.57 against 0.42 ms at degree 4); the others fit unbounded.  With
+// five rows per lane (4-lane segments) the per-cell LDS records of a block
+// allow two waves, and the registers are held to that.
 __host__ __device__ constexpr int move_min_waves(int D, int M, int RPL) {
-  return D == 3 ? (M == 3 ? (RPL == 1 ? 3 : RPL == 2 ? 2 : 1) : 1) : M <= 3 ? 3 : 2;
+  return D == 3 ? (M == 3 ? (RPL == 1 ? 3 : RPL == 2 ? 2 : 1) : 1) : M <= 3 && RPL <= 4 ? 3 : 2;
 }
 
 template <typename T>
@@ -165,16 +169,18 @@ constexpr int kDppRowShr4 = 0x114;    // lane l - 4 within each 16
 // of the wave must be active.
 template <int SEG, int N>
 __device__ __forceinline__ void seg_sum(double (&x)[N], int first = 0, int last = N) {
-  static_assert(SEG == 8 || SEG == 16 || SEG == 32 || SEG == 64, "segment of 8, 16, 32 or 64 lanes");
+  static_assert(SEG == 4 || SEG == 8 || SEG == 16 || SEG == 32 || SEG == 64, "segment of 4, 8, 16, 32 or 64 lanes");
 #pragma unroll
   for (int c = 0; c < N; ++c)
     if (c >= first && c < last) x[c] += dpp_d<kDppXor1>(x[c]);
 #pragma unroll
   for (int c = 0; c < N; ++c)
     if (c >= first && c < last) x[c] += dpp_d<kDppXor2>(x[c]);
+  if constexpr (SEG >= 8) {
 #pragma unroll
-  for (int c = 0; c < N; ++c)
-    if (c >= first && c < last) x[c] += dpp_d<kDppHalfMirror>(x[c]);
+    for (int c = 0; c < N; ++c)
+      if (c >= first && c < last) x[c] += dpp_d<kDppHalfMirror>(x[c]);
+  }
   if constexpr (SEG >= 16) {
 #pragma unroll
     for (int c = 0; c < N; ++c)
@@ -192,15 +198,17 @@ __device__ __forceinline__ void seg_sum(double (&x)[N], int first = 0, int last 
   }
 }
 
-// Value of x in lane SRC of this lane's segment.  A 16-lane segment is one
-// DPP row: the row's lane SRC is broadcast to the row (row_newbcast).  An
-// 8-lane segment is half a row: lane SRC % 4 of every quad goes to its quad
+// Value of x in lane SRC of this lane's segment.  A 4-lane segment is a quad
+// (quad_perm).  A 16-lane segment is one DPP row: the row's lane SRC is
+// broadcast to the row (row_newbcast).  An 8-lane segment is half a row: lane SRC % 4 of every quad goes to its quad
 // (quad_perm), then the quad that holds lane SRC of the segment goes to the
 // segment's other quad (a row shift by 4 written to that quad's banks only).
 template <int SEG, int SRC>
 __device__ __forceinline__ double seg_bcast(double x, int seg) {
   static_assert(SRC >= 0 && SRC < SEG, "lane of the segment");
-  if constexpr (SEG == 8) {
+  if constexpr (SEG == 4) {
+    return dpp_d<SRC * 0x55>(x);
+  } else if constexpr (SEG == 8) {
     const double a = dpp_d<(SRC % 4) * 0x55>(x);
     if constexpr (SRC < 4) return dpp_upd_d<kDppRowShr4, 0xA>(a, a);
     else return dpp_upd_d<kDppRowShl4, 0x5>(a, a);

@@ -29,7 +29,8 @@ namespace {
 
 template <int SEG, int RPL, int VB>
 hipError_t launch_vb(const MParams<real_t>& p, hipStream_t s) {
-  if constexpr (VB <= move_vb_max(CWENO_D, CWENO_M, SEG)) {
+  // only the pass sizes this shape uses (move_vb of VB variables is VB)
+  if constexpr (VB <= move_vb_max(CWENO_D, CWENO_M, SEG) && move_vb(CWENO_D, CWENO_M, SEG, VB) == VB) {
     constexpr int cpb = (kMoveThreads / 64) * (64 / SEG);
     const int64_t blocks = (p.nc + cpb - 1) / cpb;
     hipLaunchKernelGGL((moving_kernel<CWENO_D, CWENO_M, SEG, RPL, VB, real_t>), dim3((unsigned)blocks),
@@ -45,6 +46,7 @@ hipError_t launch_shape(const MParams<real_t>& p, hipStream_t s) {
   if constexpr (move_shape_ok(CWENO_D, CWENO_M, SEG, RPL)) {
     switch (move_vb(CWENO_D, CWENO_M, SEG, p.nv)) {
       case 2: return launch_vb<SEG, RPL, 2>(p, s);
+      case 4: return launch_vb<SEG, RPL, 4>(p, s);
       case 5: return launch_vb<SEG, RPL, 5>(p, s);
       case 9: return launch_vb<SEG, RPL, 9>(p, s);
     }
@@ -78,6 +80,7 @@ hipError_t CWENO_ASM_FN(CWENO_D, CWENO_M)(const MParams<double>& p, int seg, hip
 #endif
 
 hipError_t CWENO_MOVE_FN(CWENO_TN, CWENO_D, CWENO_M)(const MParams<real_t>& p, int seg, int rpl, hipStream_t s) {
+  if (seg == 4 && rpl == 5) return launch_shape<4, 5>(p, s);
   if (seg == 8 && rpl == 1) return launch_shape<8, 1>(p, s);
   if (seg == 8 && rpl == 2) return launch_shape<8, 2>(p, s);
   if (seg == 8 && rpl == 3) return launch_shape<8, 3>(p, s);
