@@ -249,9 +249,10 @@ cweno_status cweno_reconstruct_moving(const cweno_mesh* mesh, const double* vert
 /*
  * cweno_mesh_set_moving_shape / cweno_mesh_moving_shape -- the work mapping
  * of cweno_reconstruct_moving (no effect on its results beyond rounding).
- * A segment of seg lanes (8, 16, 32 or 64, or 4 with rpl = 5 for 2-D degree 3)
- * reconstructs one cell, each lane holding rpl rows (1..4) of the cell's
- * least-squares matrix; narrower
+ * A segment of seg lanes (8, 16, 32 or 64) reconstructs one cell, each lane
+ * holding rpl rows (1..4) of the cell's least-squares matrix; besides those,
+ * seg = 4 with rpl = 5 is built for 2-D degree 3 and seg = 8 with rpl = 8 for
+ * 3-D degree 3 (both the defaults there); narrower
  * segments need fewer exchange stages per sum over the rows and serve more
  * cells per wave.  By default the narrowest instantiated shape whose seg * rpl
  * row slots hold the central stencil (besides the cell) is used.

@@ -12,10 +12,13 @@ namespace cweno {
 // rows of R must lie in the segment's row slots (fewer basis functions than
 // lanes times rows per lane), three rows per lane only on 8 lanes, four only
 // on 8 or 16, two rows per lane on 64 lanes only for the wide 3-D stencils,
-// and 4 lanes of five rows each only for the 2-D degree-3 stencils (19 cells
-// besides the cell: 20 row slots against 24 on 8 lanes of three).
+// 4 lanes of five rows each only for the 2-D degree-3 stencils (19 cells
+// besides the cell: 20 row slots against 24 on 8 lanes of three), and 8 lanes
+// of eight rows each only for the 3-D degree-3 stencils (59 cells: half the
+// exchange stages per sum of 16 lanes of four, at the cost of a few spilled
+// registers and one workgroup per CU).
 __host__ __device__ constexpr bool move_shape_ok(int D, int M, int seg, int rpl) {
-  return ((seg == 4 && rpl == 5 && D == 2 && M == 3) ||
+  return ((seg == 4 && rpl == 5 && D == 2 && M == 3) || (seg == 8 && rpl == 8 && D == 3 && M == 3) ||
           ((seg == 8 || seg == 16 || seg == 32 || seg == 64) && rpl >= 1 && rpl <= 4)) &&
          nbasis_c(M, D) - 1 < seg * rpl && (rpl != 3 || seg == 8) && (rpl < 4 || seg <= 16) &&
          (seg < 64 || rpl == 1 || (D == 3 && M >= 2));
@@ -24,7 +27,7 @@ __host__ __device__ constexpr bool move_shape_ok(int D, int M, int seg, int rpl)
 // Preferred shapes, in order: the narrowest segment whose rows hold the
 // stencil, with as few rows per lane as that allows (fewer exchange stages per
 // sum, more cells per wave instruction).
-constexpr int kMoveShapes[12][2] = {{4, 5},  {8, 1},  {8, 2},  {8, 3},  {8, 4},  {16, 1},
+constexpr int kMoveShapes[13][2] = {{4, 5},  {8, 1},  {8, 2},  {8, 3},  {8, 4},  {8, 8},  {16, 1},
                                     {16, 2}, {16, 4}, {32, 1}, {32, 2}, {64, 1}, {64, 2}};
 
 // First instantiated shape whose rows hold the NE1 stencil cells besides the

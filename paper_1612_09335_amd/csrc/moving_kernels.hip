@@ -81,6 +81,7 @@ hipError_t CWENO_ASM_FN(CWENO_D, CWENO_M)(const MParams<double>& p, int seg, hip
 
 hipError_t CWENO_MOVE_FN(CWENO_TN, CWENO_D, CWENO_M)(const MParams<real_t>& p, int seg, int rpl, hipStream_t s) {
   if (seg == 4 && rpl == 5) return launch_shape<4, 5>(p, s);
+  if (seg == 8 && rpl == 8) return launch_shape<8, 8>(p, s);
   if (seg == 8 && rpl == 1) return launch_shape<8, 1>(p, s);
   if (seg == 8 && rpl == 2) return launch_shape<8, 2>(p, s);
   if (seg == 8 && rpl == 3) return launch_shape<8, 3>(p, s);

@@ -261,7 +261,8 @@ def test_bounded_moved_mesh_dropped_sectors(case, r):
     assert err32 <= TOL32
 
 
-SHAPES = [(4, 5), (8, 1), (8, 2), (8, 3), (8, 4), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2), (64, 1), (64, 2)]
+SHAPES = [(4, 5), (8, 1), (8, 2), (8, 3), (8, 4), (8, 8), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2), (64, 1),
+          (64, 2)]
 SHAPE_CASES = {
     # name: (mesh factory, degree, variables); nine variables on 8 lanes take two passes
     "tri12_M3_nv9": (lambda: tri_mesh(12, 0.15, 570), 3, 9),
@@ -297,10 +298,12 @@ def test_every_segment_shape_against_oracle(case):
             # too small for the stencil, or a shape the library does not build:
             # rows of R outside the row slots, three rows per lane off 8 lanes,
             # four rows per lane on 32 or 64 lanes, two rows per lane on 64
-            # lanes below 3-D degree 2, 4 lanes outside 2-D degree 3
+            # lanes below 3-D degree 2, 4 lanes outside 2-D degree 3, eight
+            # rows per lane outside 3-D degree 3
             not_built = (lm.n_basis - 1 >= seg * rpl or (rpl == 3 and seg != 8) or (rpl == 4 and seg > 16)
                          or (seg == 64 and rpl == 2 and not (lm.dim == 3 and M >= 2))
-                         or (seg == 4 and not (lm.dim == 2 and M == 3)))
+                         or (seg == 4 and not (lm.dim == 2 and M == 3))
+                         or (rpl == 8 and not (lm.dim == 3 and M == 3)))
             assert seg * rpl < lm.n_e - 1 or not_built, (seg, rpl)
             continue
         assert lm.moving_shape() == (seg, rpl)
